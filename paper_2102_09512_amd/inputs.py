@@ -1,0 +1,229 @@
+"""Seeded synthetic initial fields (rho, u, T) for the compressible LBM.
+
+This module holds only input generators.  It contains none of the lattice
+Boltzmann arithmetic: it builds macroscopic fields from the set-ups of the
+paper's benchmarks (Sec. III) and from textbook gas dynamics, and hands the same
+arrays to the GPU library and to the CPU oracle.
+
+All fields are FP64 numpy arrays in lattice units (R = 1, delta_x = delta_t = 1):
+rho and T of shape (nz, ny, nx), u of shape (D, nz, ny, nx); node x sits at
+coordinate x (integer), node = x + nx*(y + ny*z).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def _shape(D, dims):
+    nx, ny = int(dims[0]), int(dims[1])
+    nz = int(dims[2]) if D == 3 else 1
+    return (nz, ny, nx)
+
+
+# ---------------------------------------------------------------------------
+# Sod shock tube (Sec. III.B)
+# ---------------------------------------------------------------------------
+
+def sod(nx=800, ny=4, T_left=0.0256, rho_left=1.0, rho_right=0.125, p_ratio=0.1):
+    """Sod's Riemann problem: (rho, u, p) = (1, 0, T_l) for x < nx/2 and
+    (0.125, 0, 0.1 T_l) otherwise (the paper's left/right pressure ratio 10 and
+    density ratio 8, left pressure = left temperature T_l in lattice units)."""
+    shape = (1, ny, nx)
+    x = np.arange(nx)
+    left = (x < nx // 2)[None, None, :]
+    rho = np.where(left, rho_left, rho_right) * np.ones(shape)
+    p = np.where(left, rho_left * T_left, p_ratio * rho_left * T_left) * np.ones(shape)
+    T = p / rho
+    u = np.zeros((2,) + shape)
+    return rho, u, T
+
+
+# ---------------------------------------------------------------------------
+# Normal shock and isentropic vortex (Sec. III.C)
+# ---------------------------------------------------------------------------
+
+def rankine_hugoniot(M1, rho1, T1, gamma):
+    """Downstream state of a stationary normal shock with upstream Mach M1
+    (textbook normal-shock relations; p = rho T)."""
+    u1 = M1 * math.sqrt(gamma * T1)
+    p1 = rho1 * T1
+    r = (gamma + 1.0) * M1 * M1 / ((gamma - 1.0) * M1 * M1 + 2.0)
+    p2 = p1 * (1.0 + 2.0 * gamma / (gamma + 1.0) * (M1 * M1 - 1.0))
+    rho2 = rho1 * r
+    u2 = u1 / r
+    return dict(rho1=rho1, u1=u1, T1=T1, p1=p1, rho2=rho2, u2=u2, p2=p2, T2=p2 / rho2)
+
+
+def shock_vortex(nx=1024, ny=1024, Ma_a=1.2, Ma_v=0.25, r_v=32.0, x_s=None, x_v=None, y_v=None,
+                 T_l=0.05, rho_l=1.0, gamma=1.4, vortex=True):
+    """Standing normal shock at x_s with an isentropic vortex of radius r_v at
+    (x_v, y_v).  Upstream (x < x_s) state (rho, T, u_x, u_y) = (rho_l, T_l,
+    Ma_a sqrt(gamma T_l), 0), Rankine-Hugoniot downstream.  The vortex formula
+    of Sec. III.C perturbs the local base state (rho_inf, P_inf, u_inf)."""
+    if x_s is None:
+        x_s = nx // 2
+    if x_v is None:
+        x_v = x_s - 2.0 * r_v
+    if y_v is None:
+        y_v = ny / 2.0
+    rh = rankine_hugoniot(Ma_a, rho_l, T_l, gamma)
+    x = np.arange(nx, dtype=np.float64)[None, :]
+    y = np.arange(ny, dtype=np.float64)[:, None]
+    up = x < x_s
+    rho_inf = np.where(up, rh["rho1"], rh["rho2"]) * np.ones((ny, nx))
+    p_inf = np.where(up, rh["p1"], rh["p2"]) * np.ones((ny, nx))
+    ux_inf = np.where(up, rh["u1"], rh["u2"]) * np.ones((ny, nx))
+    rho, p, ux, uy = rho_inf, p_inf, ux_inf, np.zeros((ny, nx))
+    if vortex:
+        r2 = ((x - x_v) ** 2 + (y - y_v) ** 2) / (r_v * r_v)
+        b = 1.0 - 0.5 * (gamma - 1.0) * Ma_v * Ma_v * np.exp(1.0 - r2)
+        rho = rho_inf * b ** (1.0 / (gamma - 1.0))
+        p = p_inf * b ** (gamma / (gamma - 1.0))
+        a = math.sqrt(gamma * T_l) * Ma_v * np.exp(0.5 * (1.0 - r2)) / r_v
+        ux = ux_inf + a * (y - y_v)
+        uy = -a * (x - x_v)
+    T = p / rho
+    u = np.stack([ux, uy])[:, None, :, :]
+    return rho[None], u, T[None], rh
+
+
+def shock_vortex_viscosity(Re=800.0, r_v=32.0, T_l=0.05, rho_l=1.0, gamma=1.4):
+    """mu from Re = rho_l c_{s,l} r_v / mu (Sec. III.C)."""
+    return rho_l * math.sqrt(gamma * T_l) * r_v / Re
+
+
+# ---------------------------------------------------------------------------
+# Decaying isotropic turbulence (Sec. III.D)
+# ---------------------------------------------------------------------------
+
+def turbulence(D, n, seed, k0_index=4, Ma_t=0.5, T0=0.15, rho0=1.0, gamma=1.4):
+    """Divergence-free random velocity with shell spectrum
+    E(k) = A k^4 exp(-2 (k/k0)^2), k0 = k0_index * 2 pi / n, scaled so that
+    sqrt(<u.u>) = Ma_t <c_s> with c_s = sqrt(gamma T0); rho = rho0, T = T0.
+
+    Random-phase Fourier synthesis (the paper names kinematic simulation but
+    does not describe it): every integer wave vector gets a random direction
+    orthogonal to k (solenoidal) and a random phase, with an amplitude that
+    makes each integer shell carry exactly the target spectrum; the spectrum is
+    made Hermitian so the field is real.  Fields of different n are cubes
+    (D = 3) or squares (D = 2)."""
+    rng = np.random.default_rng(seed)
+    shape = (n,) * D
+    freqs = np.fft.fftfreq(n, d=1.0 / n)  # integer wave numbers
+    K = np.stack(np.meshgrid(*([freqs] * D), indexing="ij"))  # K[a] = k_a over axes (a0, a1, ...)
+    kmag = np.sqrt((K ** 2).sum(0))
+    shell = np.rint(kmag).astype(np.int64)
+    # random complex vectors, projected orthogonal to k, normalised to unit length
+    a = rng.standard_normal((D,) + shape) + 1j * rng.standard_normal((D,) + shape)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        kdota = (K * a).sum(0) / np.where(kmag > 0, kmag ** 2, 1.0)
+    a = a - K * kdota
+    norm = np.sqrt((np.abs(a) ** 2).sum(0))
+    a = a / np.where(norm > 0, norm, 1.0)
+    # shell amplitude: sum over a shell of |u_hat|^2 / 2 = E(shell) (up to a global factor)
+    kk = np.arange(shell.max() + 1, dtype=np.float64)
+    E = kk ** 4 * np.exp(-2.0 * (kk / k0_index) ** 2)
+    count = np.bincount(shell.ravel(), minlength=kk.size).astype(np.float64)
+    amp2 = np.where(count > 0, 2.0 * E / np.maximum(count, 1.0), 0.0)
+    amp = np.sqrt(amp2[shell])
+    nyq = np.zeros(shape, dtype=bool)
+    for ax in range(D):
+        nyq |= np.abs(K[ax]) == n // 2 if n % 2 == 0 else np.zeros(shape, dtype=bool)
+    amp = np.where(nyq | (kmag == 0), 0.0, amp)
+    uh = a * amp
+    # Hermitian: keep a canonical half-space, mirror the rest as conj(u_hat(-k))
+    idx = np.indices(shape)
+    minus = tuple((-idx[ax]) % n for ax in range(D))
+    canon = np.zeros(shape, dtype=bool)
+    decided = np.zeros(shape, dtype=bool)
+    for ax in range(D - 1, -1, -1):  # last axis first, then lexicographic tie-break
+        pos = (K[ax] > 0) & ~decided
+        negm = (K[ax] < 0) & ~decided
+        canon |= pos
+        decided |= pos | negm
+    uh = np.where(canon[None], uh, np.conj(uh[(slice(None),) + minus]))
+    u = np.fft.ifftn(uh, axes=tuple(range(1, D + 1))).real
+    # array axes are (a0, a1, a2) = (x, y, z) in meshgrid 'ij' order; store as (z, y, x)
+    u = np.stack([u[c] for c in range(D)])
+    u = np.transpose(u, (0,) + tuple(range(D, 0, -1)))
+    cs = math.sqrt(gamma * T0)
+    scale = Ma_t * cs / math.sqrt((u ** 2).sum(0).mean())
+    u = u * scale
+    if D == 2:
+        u = u[:, None, :, :]
+    sh = u.shape[1:]
+    rho = np.full(sh, rho0)
+    T = np.full(sh, T0)
+    return rho, u, T
+
+
+def turbulence_viscosity(n, k0_index=4, Ma_t=0.5, T0=0.15, rho0=1.0, gamma=1.4, Re_lambda=72.0, D=3):
+    """mu_0 from Re_lambda = <rho> u_rms lambda / mu_0 (Sec. III.D) with
+    u_rms = sqrt(<u.u>/D) and the Taylor microscale of the initial spectrum,
+    lambda = sqrt(<u_x^2>/<(d_x u_x)^2>) = 2/k0 (the closed form for
+    E ~ k^4 exp(-2 k^2/k0^2) in 3D)."""
+    k0 = k0_index * 2.0 * math.pi / n
+    u_rms = Ma_t * math.sqrt(gamma * T0) / math.sqrt(D)
+    lam = 2.0 / k0
+    return rho0 * u_rms * lam / Re_lambda
+
+
+# ---------------------------------------------------------------------------
+# Small test fields
+# ---------------------------------------------------------------------------
+
+def smooth_random(D, dims, seed, rho_amp=0.05, u_amp=0.05, T0=0.15, T_amp=0.02, modes=3):
+    """Smooth periodic random fields built from a few low Fourier modes."""
+    rng = np.random.default_rng(seed)
+    shape = _shape(D, dims)
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+
+    def field(amp):
+        f = np.zeros(shape)
+        for _ in range(modes):
+            kx, ky = rng.integers(0, 3, size=2)
+            kz = rng.integers(0, 3) if D == 3 else 0
+            ph = rng.uniform(0, 2 * math.pi)
+            f += np.cos(2 * math.pi * (kx * x / nx + ky * y / ny + kz * z / nz) + ph)
+        return amp * f / modes
+
+    rho = 1.0 + field(rho_amp)
+    T = T0 + field(T_amp)
+    u = np.stack([field(u_amp) for _ in range(D)])
+    return rho, u, T
+
+
+def uniform(D, dims, rho=1.0, u=(0.0, 0.0, 0.0), T=0.15):
+    shape = _shape(D, dims)
+    return (np.full(shape, float(rho)), np.stack([np.full(shape, float(u[a])) for a in range(D)]),
+            np.full(shape, float(T)))
+
+
+def linear_wave(D, n, kind, eps=1e-4, rho0=1.0, T0=0.15, U=0.0, gamma=1.4, mode=1):
+    """One-dimensional linear perturbations along x on a D-dimensional box of
+    n x 1 (x 1) nodes: kind = 'acoustic' (isentropic pressure pulse,
+    u = 0), 'shear' (u_y = eps sin(kx)) or 'entropy' (T' = eps cos(kx) at
+    uniform p).  U adds a uniform background velocity along x."""
+    dims = (n, 1, 1)
+    rho, u, T = uniform(D, dims, rho0, (U, 0.0, 0.0), T0)
+    x = np.arange(n, dtype=np.float64)
+    k = 2.0 * math.pi * mode / n
+    c = np.cos(k * x)[None, None, :]
+    if kind == "acoustic":
+        p0 = rho0 * T0
+        dp = eps * p0 * c
+        drho = dp / (gamma * T0)          # isentropic: drho = dp / c_s^2
+        rho = rho + drho
+        T = (p0 + dp) / rho
+    elif kind == "shear":
+        u[1] = u[1] + eps * np.sin(k * x)[None, None, :]
+    elif kind == "entropy":
+        p0 = rho0 * T0
+        T = T0 * (1.0 + eps * c) * np.ones_like(T)
+        rho = p0 / T
+    else:
+        raise ValueError(kind)
+    return rho, u, T
