@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Throughput of the fused stream-and-collide on one MI355X.
+
+Workload (default): 3-D compressible decaying turbulence, D3Q27, 256^3
+periodic nodes, FP32 deviation storage; seeded solenoidal velocity with
+E(k) ~ k^4 exp(-2 (k/k0)^2), k0 = 4 (2 pi/256), Ma_t = 0.5, Re_lambda = 72,
+rho = 1, T0 = 0.15, mu = mu0 (T/T0)^0.76, Pr = 0.7, gamma = 1.4.
+
+One timed step = one lbm_step (one launch of the fused kernel) over the whole
+box; the diagnostics reduction runs every --diag-every steps inside the timed
+region.  Prints one JSON line (metric MLUPS) with the roofline of the step
+kernel (algorithmic bytes per node update 2 x Q x (read + write) x 4 B = 432 B)
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("lbm_kernels.hip", "lbm_node.h", "lbm_internal.h"):
+        with open(os.path.join(ROOT, "paper_2102_09512_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, precision: str):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    for r in rec.get("records", []):
+        if r.get("workload") == workload and r.get("precision") == precision and r.get("source") == kernel_source_hash():
+            return r.get("bytes_per_launch")
+    return None
+
+
+def cpu_baseline(fields, dims, mu, budget_s: float):
+    """The oracle as it stands, on the GPU host's cores, over whole steps of
+    the same 256^3 input until about budget_s seconds of stepping."""
+    import oracle
+
+    threads = oracle.num_threads()
+    _log(f"[cpu baseline] oracle with {threads} threads on {dims}")
+    s = oracle.Sim(3, dims, gamma=1.4, Pr=0.7, mu=mu, visc_exp=0.76, T_ref=0.15)
+    s.init(*fields)
+    N = dims[0] * dims[1] * dims[2]
+    steps, t_total = 0, 0.0
+    while t_total < budget_s and steps < 50:
+        t0 = time.perf_counter()
+        s.step(1)
+        t_total += time.perf_counter() - t0
+        steps += 1
+        _log(f"[cpu baseline] step {steps}: {t_total:.1f} s")
+    del s
+    return {"value": N * steps / t_total / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} full step(s) of the same {dims[0]}x{dims[1]}x{dims[2]} D3Q27 input, FP64, "
+                      f"{t_total:.1f} s of stepping (initialisation excluded)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=256, help="box edge (default: the 256^3 workload)")
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--tile", type=str, default="", help="bx,by,chunk of the step kernel")
+    ap.add_argument("--diag-every", type=int, default=100)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=2048, help="size of the copy-kernel reference")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "decomposition is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2102_09512_amd import inputs, lbm
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    n = args.n
+    dims = (n, n, n)
+    N = n ** 3
+    Q = 27
+    word = 4 if args.precision == "fp32" else 8
+    bytes_per_node = 2 * Q * 2 * word
+
+    _log(f"[bench] generating the {n}^3 turbulence input")
+    fields = inputs.turbulence(3, n, seed=0, k0_index=4, Ma_t=0.5, T0=0.15)
+    mu = inputs.turbulence_viscosity(n, k0_index=4, Ma_t=0.5, T0=0.15, Re_lambda=72.0)
+
+    stream = torch.cuda.current_stream(dev)
+    tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
+    h = lbm.lbm_create(3, dims, 1.4, 0.7, mu, precision=lbm.LBM_FP32_DEV if word == 4 else lbm.LBM_FP64,
+                       visc_exponent=0.76, T_ref=0.15, rho_ref=1.0, tile=tile)
+    lbm.lbm_set_stream(h, stream)
+    lbm.lbm_init_fields(h, *(torch.from_numpy(a).to(dev) for a in fields))
+
+    _log(f"[bench] warmup {args.warmup} steps")
+    lbm.lbm_step(h, args.warmup)
+    torch.cuda.synchronize()
+
+    # timed region: K steps, diagnostics every diag_every steps; events on the
+    # stream the library launches on bracket every step launch
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    diags = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        lbm.lbm_step(h, 1)
+        ends[k].record(stream)
+        if args.diag_every and (k + 1) % args.diag_every == 0:
+            diags.append(lbm.lbm_diagnostics(h))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    avg_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
+    _log(f"[bench] {args.steps} steps in {wall:.3f} s; step kernel avg {avg_kernel_s * 1e3:.3f} ms "
+         f"(min {min(kernel_ms):.3f}, max {max(kernel_ms):.3f})")
+    d = lbm.lbm_diagnostics(h)
+    if d["nonfinite"] or d["nonpositive"]:
+        _log("[bench] WARNING: the state has non-finite or non-positive values")
+    lbm.lbm_destroy(h)
+
+    # reference: the library's own copy kernel over a large buffer
+    copy_gbps = None
+    if args.copy_mib:
+        nb = args.copy_mib * 1024 * 1024
+        a = torch.empty(nb // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            lbm.lbm_device_copy(b, a, nb, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record(stream)
+        for _ in range(reps):
+            lbm.lbm_device_copy(b, a, nb, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        copy_gbps = 2 * nb * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+        del a, b
+        _log(f"[bench] copy kernel {copy_gbps:.0f} GB/s")
+
+    mlups = N * args.steps / wall / 1e6
+    achieved = bytes_per_node * N / avg_kernel_s / 1e9
+    workload = f"decaying-turbulence D3Q27 {n}^3 periodic {args.precision}-storage Ma_t=0.5 Re_lambda=72"
+    traffic = measured_traffic(workload, args.precision)
+    out = {
+        "metric": "MLUPS (D3Q27 fused stream+collide)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if word == 4 else "f64",
+        "data": "synthetic (seeded solenoidal turbulence, no dataset)",
+        "config": {"workload": workload, "lattice": "D3Q27", "nodes": N, "dims": list(dims),
+                   "bytes_per_node_update": bytes_per_node, "diag_every": args.diag_every,
+                   "tile": list(tile) if tile else "default", "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                     "kernel": "step_kernel", "avg_kernel_ms": round(avg_kernel_s * 1e3, 4),
+                     "algorithmic_bytes_per_launch": bytes_per_node * N},
+        "copy_kernel_GBps": round(copy_gbps, 1) if copy_gbps else None,
+        "hbm_fraction_of_copy": round(achieved / copy_gbps, 4) if copy_gbps else None,
+        "kernel_source": kernel_source_hash(),
+        "final_step_nonfinite": d["nonfinite"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(fields, dims, mu, args.cpu_seconds)
+        out["cpu_baseline"]["gpu_speedup"] = round(mlups / out["cpu_baseline"]["value"], 1)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

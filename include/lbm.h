@@ -1,0 +1,146 @@
+/*
+ * lbm.h - C ABI of the MI355X library for the two-population compressible
+ * lattice Boltzmann model of Saadat, Hosseini, Dorschner and Karlin,
+ * "Extended lattice Boltzmann model for gas dynamics" (arXiv:2102.09512).
+ *
+ * One call of lbm_step advances the state by one time step of the kinetic
+ * equations (1) (f: mass and momentum, BGK relaxation to the extended
+ * equilibrium of Eqs. (28)-(30)) and (2) (g: total energy, relaxation to the
+ * equilibrium of Eq. (42) and the quasi-equilibrium of Eqs. (44), (46)), with
+ * the anomaly derivative of Sec. III.A computed from the post-streaming
+ * moments of the same step.  All of it runs in HIP kernels for gfx950.
+ *
+ * Conventions
+ *   - Lattice units: delta_t = delta_x = 1, R = 1; constant specific heats
+ *     C_v = 1/(gamma-1) (Sec. III.A).
+ *   - Fields are FP64, node-major, node = x + nx*(y + ny*z).  rho[N], T[N];
+ *     u holds D consecutive planes u_x[N], u_y[N] (, u_z[N]).
+ *   - Population numbering: c_i = (i%3-1, (i/3)%3-1, (i/9)%3-1), Q = 3^D; the
+ *     opposite of i is Q-1-i.
+ *   - Every call returns an int: LBM_OK (0) or a negative error code; nothing
+ *     aborts or throws across the ABI.  lbm_last_error gives the message of
+ *     the last failure on the calling thread.
+ *   - Ownership: the handle owns all device population buffers.  The caller
+ *     owns every array it passes and keeps it alive until the call returns
+ *     (for LBM_DEVICE arrays: until the bound stream has passed the call).
+ *     The library keeps no caller pointer.
+ *   - Streams: work is ordered on the stream given to lbm_set_stream (default:
+ *     the null stream of the device that was current at lbm_create).  Calls
+ *     with LBM_HOST arrays and lbm_diagnostics synchronise that stream; the
+ *     others are asynchronous.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx* lbm_handle;
+
+/* Lattices: value = D.  D3Q27 is Eq. (8); D2Q9 drops the z factor of the
+   product form (Eq. (12)). */
+enum { LBM_D2Q9 = 2, LBM_D3Q27 = 3 };
+/* Population storage.  LBM_FP32_DEV stores f_i - f^eq_i(rho_ref, 0, T_ref)
+   and g_i - g^eq_i(rho_ref, 0, T_ref) in FP32 and collides in FP32; mass,
+   momentum and energy sums and the temperature recovery are FP64. */
+enum { LBM_FP64 = 0, LBM_FP32_DEV = 1 };
+/* Boundaries, per axis (both ends): periodic wrap, or zero-gradient (the
+   streaming source and every difference neighbour are clamped to the domain). */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_ZERO_GRADIENT = 1 };
+/* Where caller arrays live. */
+enum { LBM_HOST = 0, LBM_DEVICE = 1 };
+/* Discrete derivative of the anomaly: first-order upwind (Sec. III.A) or
+   second-order central (Sec. III.D.2). */
+enum { LBM_DERIV_UPWIND = 0, LBM_DERIV_CENTRAL = 1 };
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,    /* bad argument or field value */
+  LBM_ENOMEM = -2,    /* device allocation failed */
+  LBM_EDEVICE = -3,   /* a HIP call failed (message in lbm_last_error) */
+  LBM_EUNSTABLE = -4, /* the last diagnostics found non-finite or non-positive rho/T */
+  LBM_ESTATE = -5     /* call out of order (e.g. lbm_step before lbm_init_fields) */
+};
+
+typedef struct {
+  int precision;        /* LBM_FP64 (default) or LBM_FP32_DEV */
+  int bc[3];            /* per axis; default LBM_BC_PERIODIC */
+  double visc_exponent; /* mu = mu0 (T/T_ref)^visc_exponent (Sec. III.D); 0 = constant mu (default) */
+  double T_ref;         /* T_0 of the power law and rest temperature of FP32 deviations; default 1/3 */
+  double rho_ref;       /* rest density of FP32 deviations; default 1 */
+  int deriv_scheme;     /* LBM_DERIV_UPWIND (default) or LBM_DERIV_CENTRAL */
+  int tile[3];          /* launch shape of the step kernel: x width, y width (D3Q27), march chunk; 0 = default */
+} lbm_options;
+
+/* Fills *opt with the defaults above. */
+void lbm_default_options(lbm_options* opt);
+
+/* Whole-field sums of the stored state (the post-collision populations;
+   moments without streaming).  Derivatives are central differences with the
+   same wrap/clamp rule as the method. */
+typedef struct {
+  int64_t step;
+  int64_t nodes;
+  double mass;              /* sum rho */
+  double momentum[3];       /* sum rho u */
+  double energy;            /* sum rho E = sum of all g_i */
+  double kinetic_energy;    /* sum rho |u|^2 / 2 */
+  double dilatation_sq_sum; /* sum (div u)^2 */
+  double u2_sum;            /* sum |u|^2 */
+  double cs_sum;            /* sum sqrt(gamma T) */
+  double rho2_sum;          /* sum rho^2 */
+  double vorticity_sq_sum;  /* sum |curl u|^2 */
+  double dissipation_sum;   /* sum mu(T) |curl u|^2 */
+  double u_axis_sq_sum[3];  /* sum u_a^2 */
+  double du_axis_sq_sum[3]; /* sum (d_a u_a)^2 */
+  int64_t nonfinite;        /* nodes with a non-finite rho, u or T */
+  int64_t nonpositive;      /* nodes with rho <= 0 or T <= 0 */
+} lbm_diag;
+
+/* Creates a simulation on the current HIP device.
+   lattice: LBM_D2Q9 or LBM_D3Q27; dims: nx, ny, nz (nz must be 1 for D2Q9);
+   gamma > 1 (Eq. (97)); Pr > 0 (Eq. (96)); mu > 0 the dynamic viscosity (at
+   T_ref when a power law is set), Eq. (92).  opt may be NULL (defaults).
+   Allocates the two population buffers (2 x 2Q x N values).  Returns
+   LBM_EINVAL before any device work on a bad argument; *out is NULL on error. */
+int lbm_create(lbm_handle* out, int lattice, const int64_t dims[3], double gamma, double Pr, double mu,
+               const lbm_options* opt);
+/* Frees everything the handle owns.  NULL is accepted. */
+int lbm_destroy(lbm_handle h);
+/* Binds a hipStream_t for all later work of this handle. */
+int lbm_set_stream(lbm_handle h, void* hip_stream);
+/* Sets f = f^eq(rho,u,T) (Eq. (20)) and g = g^eq(rho,u,T) (Eq. (42)), step = 0.
+   LBM_EINVAL if any value is non-finite or rho <= 0 or T <= 0 (nothing is
+   changed then).  mem: LBM_HOST or LBM_DEVICE. */
+int lbm_init_fields(lbm_handle h, const double* rho, const double* u, const double* T, int mem);
+/* Advances n >= 0 steps (one fused stream-and-collide launch per step).
+   LBM_ESTATE before lbm_init_fields; LBM_EUNSTABLE if the last lbm_diagnostics
+   found a bad node. */
+int lbm_step(lbm_handle h, int64_t n);
+/* rho, u, T of the stored populations (Eqs. (3)-(7) without streaming).  Any
+   output pointer may be NULL. */
+int lbm_moments(lbm_handle h, double* rho, double* u, double* T, int mem);
+/* Synchronous reductions over the stored state (FP64, fixed order). */
+int lbm_diagnostics(lbm_handle h, lbm_diag* out);
+/* Raw state for checkpoints: 2Q population planes of N values (f then g) in
+   the storage type (FP64: double values; FP32_DEV: float deviations). */
+size_t lbm_state_bytes(lbm_handle h);
+int lbm_get_state(lbm_handle h, void* buf, size_t bytes, int mem);
+/* Restores a state written by lbm_get_state of a handle with the same lattice,
+   dims and precision; the step counter is set to step. */
+int lbm_set_state(lbm_handle h, const void* buf, size_t bytes, int mem, int64_t step);
+int64_t lbm_step_count(lbm_handle h);
+/* Message of the last failure on this thread ("" if none).  h is unused. */
+const char* lbm_last_error(lbm_handle h);
+/* Plain device-to-device copy of bytes (multiple of 16) on hip_stream, by the
+   library's own vectorised copy kernel: the reference for achievable HBM
+   bandwidth and for scaling hardware byte counters. */
+int lbm_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,76 @@
+// Internal declarations shared by the host API and the kernel launchers of
+// liblbm.so.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "lbm.h"
+
+namespace lbm {
+
+// Everything the step kernel needs, passed by value.
+struct StepParams {
+  int nx, ny, nz;
+  int bc[3];            // LBM_BC_* per axis
+  long long ps;         // elements between consecutive population arrays
+  int tiles_x, tiles_y; // in-plane tiles (tiles_y == 1 for D2Q9)
+  int chunks, chunk_len;// march-axis chunks (z for D3Q27, y for D2Q9)
+  int nblocks;
+  int deriv;            // LBM_DERIV_*
+  double rho0, T0, rhoE0;   // rest state of the deviation storage (all 0 for FP64 storage)
+  double Cv, inv_Cv, Pr;
+  double mu0, visc_exp, inv_Tref;
+  double gamma;
+};
+
+// Launch shape of the step kernel (compile-time instantiations).
+struct Tile {
+  int bx, by, chunk;
+};
+
+struct Ctx {
+  int lattice = 0;      // D
+  int Q = 0;
+  int precision = 0;
+  int64_t n[3] = {1, 1, 1};
+  int64_t N = 0;
+  long long ps = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  double gamma = 1.4, Pr = 0.71, mu = 0.01;
+  lbm_options opt{};
+  Tile tile{};
+  void* buf[2] = {nullptr, nullptr}; // population buffers (2Q x ps elements each)
+  int cur = 0;                       // buffer holding the current state
+  double* fields = nullptr;          // 6 x N doubles: rho, ux, uy, uz, T, rhoE
+  double* partial = nullptr;         // per-block partial sums
+  double* diag_dev = nullptr;        // final sums
+  int partial_blocks = 0;
+  bool initialised = false;
+  bool unstable = false;
+  int64_t step = 0;
+  StepParams sp{};
+};
+
+constexpr int kNumDiag = 21;  // slots of the diagnostic reduction (see lbm_kernels.hip)
+
+// ---- launchers (lbm_kernels.hip) -------------------------------------------
+hipError_t launch_step(const Ctx& c, const void* src, void* dst);
+hipError_t launch_init(const Ctx& c, const double* rho, const double* u, const double* T, void* dst);
+hipError_t launch_fields(const Ctx& c, const void* pops, double* fields);
+hipError_t launch_diag(const Ctx& c, const double* fields, double* partial, int nblocks, double* out);
+int diag_blocks(const Ctx& c);
+hipError_t launch_validate(const Ctx& c, const double* rho, const double* u, const double* T, double* partial,
+                           int nblocks, double* out);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// Default launch tile for a lattice/precision and whether a tile is available.
+Tile default_tile(int D, int precision, const int64_t n[3]);
+bool tile_supported(int D, int precision, const Tile& t);
+
+}  // namespace lbm
+
+// The opaque handle type of the C ABI.
+struct lbm_ctx : public lbm::Ctx {};

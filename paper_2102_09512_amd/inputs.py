@@ -156,7 +156,7 @@ def turbulence(D, n, seed, k0_index=4, Ma_t=0.5, T0=0.15, rho0=1.0, gamma=1.4):
     sh = u.shape[1:]
     rho = np.full(sh, rho0)
     T = np.full(sh, T0)
-    return rho, u, T
+    return rho, np.ascontiguousarray(u), T
 
 
 def turbulence_viscosity(n, k0_index=4, Ma_t=0.5, T0=0.15, rho0=1.0, gamma=1.4, Re_lambda=72.0, D=3):

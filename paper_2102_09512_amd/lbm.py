@@ -1,0 +1,237 @@
+"""Python binding of liblbm.so (include/lbm.h): argument marshalling only.
+
+Every function has the name of the C entry point it calls.  Arrays may be
+numpy arrays (host memory) or torch tensors on the GPU (device memory); torch
+is used for device memory and streams only.  A missing or unloadable library
+raises at import of this module: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+LBM_D2Q9, LBM_D3Q27 = 2, 3
+LBM_FP64, LBM_FP32_DEV = 0, 1
+LBM_BC_PERIODIC, LBM_BC_ZERO_GRADIENT = 0, 1
+LBM_HOST, LBM_DEVICE = 0, 1
+LBM_DERIV_UPWIND, LBM_DERIV_CENTRAL = 0, 1
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{message} (code {code})")
+        self.code = code
+
+
+class lbm_options(C.Structure):
+    _fields_ = [
+        ("precision", C.c_int), ("bc", C.c_int * 3), ("visc_exponent", C.c_double),
+        ("T_ref", C.c_double), ("rho_ref", C.c_double), ("deriv_scheme", C.c_int),
+        ("tile", C.c_int * 3),
+    ]
+
+
+class lbm_diag(C.Structure):
+    _fields_ = [
+        ("step", C.c_int64), ("nodes", C.c_int64), ("mass", C.c_double), ("momentum", C.c_double * 3),
+        ("energy", C.c_double), ("kinetic_energy", C.c_double), ("dilatation_sq_sum", C.c_double),
+        ("u2_sum", C.c_double), ("cs_sum", C.c_double), ("rho2_sum", C.c_double),
+        ("vorticity_sq_sum", C.c_double), ("dissipation_sum", C.c_double),
+        ("u_axis_sq_sum", C.c_double * 3), ("du_axis_sq_sum", C.c_double * 3),
+        ("nonfinite", C.c_int64), ("nonpositive", C.c_int64),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'` "
+                          "(hipcc for gfx950)")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, dp = C.c_void_p, C.c_int64, C.POINTER(C.c_double)
+    L.lbm_default_options.argtypes = [C.POINTER(lbm_options)]
+    L.lbm_default_options.restype = None
+    L.lbm_create.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(i64), C.c_double, C.c_double, C.c_double,
+                             C.POINTER(lbm_options)]
+    L.lbm_destroy.argtypes = [vp]
+    L.lbm_set_stream.argtypes = [vp, vp]
+    L.lbm_init_fields.argtypes = [vp, vp, vp, vp, C.c_int]
+    L.lbm_step.argtypes = [vp, i64]
+    L.lbm_moments.argtypes = [vp, vp, vp, vp, C.c_int]
+    L.lbm_diagnostics.argtypes = [vp, C.POINTER(lbm_diag)]
+    L.lbm_state_bytes.argtypes = [vp]
+    L.lbm_state_bytes.restype = C.c_size_t
+    L.lbm_get_state.argtypes = [vp, vp, C.c_size_t, C.c_int]
+    L.lbm_set_state.argtypes = [vp, vp, C.c_size_t, C.c_int, i64]
+    L.lbm_step_count.argtypes = [vp]
+    L.lbm_step_count.restype = i64
+    L.lbm_last_error.argtypes = [vp]
+    L.lbm_last_error.restype = C.c_char_p
+    L.lbm_device_copy.argtypes = [vp, vp, C.c_size_t, vp]
+    for name in ("lbm_create", "lbm_destroy", "lbm_set_stream", "lbm_init_fields", "lbm_step", "lbm_moments",
+                 "lbm_diagnostics", "lbm_get_state", "lbm_set_state", "lbm_device_copy"):
+        getattr(L, name).restype = C.c_int
+    return L
+
+
+_L = _load()
+
+
+def _check(rc: int) -> int:
+    if rc != LBM_OK:
+        raise LbmError(rc, lbm_last_error())
+    return rc
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _arg(x, dtype=np.float64):
+    """(pointer, memory kind, keep-alive) of a numpy array or a torch tensor;
+    dtype None accepts any element type."""
+    if x is None:
+        return None, None, None
+    if _is_torch(x):
+        import torch
+
+        if dtype is not None:
+            want = torch.float64 if dtype == np.float64 else torch.float32
+            if x.dtype != want:
+                raise TypeError(f"expected a {want} tensor, got {x.dtype}")
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return x.data_ptr(), (LBM_DEVICE if x.is_cuda else LBM_HOST), x
+    if dtype is None:
+        if not (isinstance(x, np.ndarray) and x.flags.c_contiguous):
+            raise TypeError("expected a C-contiguous numpy array")
+        return x.ctypes.data, LBM_HOST, x
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return a.ctypes.data, LBM_HOST, a
+
+
+def _same_kind(*kinds):
+    ks = {k for k in kinds if k is not None}
+    if len(ks) > 1:
+        raise ValueError("all arrays of one call must be in the same memory (host or device)")
+    return ks.pop() if ks else LBM_HOST
+
+
+# ---- entry points ----------------------------------------------------------
+
+def lbm_default_options() -> lbm_options:
+    o = lbm_options()
+    _L.lbm_default_options(C.byref(o))
+    return o
+
+
+def lbm_create(lattice, dims, gamma, Pr, mu, options: lbm_options | None = None, *, precision=None, bc=None,
+               visc_exponent=None, T_ref=None, rho_ref=None, deriv_scheme=None, tile=None) -> int:
+    o = options if options is not None else lbm_default_options()
+    if precision is not None:
+        o.precision = precision
+    if bc is not None:
+        for a in range(3):
+            o.bc[a] = int(bc[a])
+    if visc_exponent is not None:
+        o.visc_exponent = visc_exponent
+    if T_ref is not None:
+        o.T_ref = T_ref
+    if rho_ref is not None:
+        o.rho_ref = rho_ref
+    if deriv_scheme is not None:
+        o.deriv_scheme = deriv_scheme
+    if tile is not None:
+        for a in range(3):
+            o.tile[a] = int(tile[a])
+    d = (C.c_int64 * 3)(*[int(v) for v in (list(dims) + [1] * (3 - len(dims)))])
+    h = C.c_void_p()
+    _check(_L.lbm_create(C.byref(h), int(lattice), d, float(gamma), float(Pr), float(mu), C.byref(o)))
+    return h.value
+
+
+def lbm_destroy(h) -> int:
+    return _check(_L.lbm_destroy(h))
+
+
+def lbm_set_stream(h, stream) -> int:
+    """stream: a torch.cuda.Stream, a raw hipStream_t integer, or None (null stream)."""
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    return _check(_L.lbm_set_stream(h, stream))
+
+
+def lbm_init_fields(h, rho, u, T) -> int:
+    pr, kr, _kr = _arg(rho)
+    pu, ku, _ku = _arg(u)
+    pt, kt, _kt = _arg(T)
+    return _check(_L.lbm_init_fields(h, pr, pu, pt, _same_kind(kr, ku, kt)))
+
+
+def lbm_step(h, n: int = 1) -> int:
+    return _check(_L.lbm_step(h, int(n)))
+
+
+def lbm_moments(h, rho=None, u=None, T=None):
+    """Writes into the given arrays (numpy or device tensors) and returns them."""
+    args = [_arg(x) for x in (rho, u, T)]
+    kind = _same_kind(*[a[1] for a in args])
+    if kind == LBM_HOST:
+        for x in (rho, u, T):
+            if x is not None and not _is_torch(x) and not (isinstance(x, np.ndarray) and x.dtype == np.float64
+                                                           and x.flags.c_contiguous):
+                raise TypeError("host outputs must be C-contiguous float64 numpy arrays")
+    _check(_L.lbm_moments(h, args[0][0], args[1][0], args[2][0], kind))
+    return rho, u, T
+
+
+def lbm_diagnostics(h) -> dict:
+    d = lbm_diag()
+    _check(_L.lbm_diagnostics(h, C.byref(d)))
+    out = {}
+    for name, _ in lbm_diag._fields_:
+        v = getattr(d, name)
+        out[name] = list(v) if isinstance(v, C.Array) else v
+    return out
+
+
+def lbm_state_bytes(h) -> int:
+    return int(_L.lbm_state_bytes(h))
+
+
+def _nbytes(buf) -> int:
+    return buf.numel() * buf.element_size() if _is_torch(buf) else buf.nbytes
+
+
+def lbm_get_state(h, buf) -> int:
+    p, k, _keep = _arg(buf, dtype=None)
+    return _check(_L.lbm_get_state(h, p, _nbytes(buf), k))
+
+
+def lbm_set_state(h, buf, step: int = 0) -> int:
+    p, k, _keep = _arg(buf, dtype=None)
+    return _check(_L.lbm_set_state(h, p, _nbytes(buf), k, int(step)))
+
+
+def lbm_step_count(h) -> int:
+    return int(_L.lbm_step_count(h))
+
+
+def lbm_last_error(h=None) -> str:
+    return _L.lbm_last_error(h).decode()
+
+
+def lbm_device_copy(dst, src, nbytes: int, stream=None) -> int:
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    return _check(_L.lbm_device_copy(dst.data_ptr(), src.data_ptr(), int(nbytes), stream))
+
+
+def raw():
+    """The ctypes library object (for the ABI tests)."""
+    return _L

@@ -1,0 +1,80 @@
+"""The C-ABI library loads and exports every entry point of include/lbm.h,
+and its host-side argument checks answer before any device work (runs
+without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    from paper_2102_09512_amd import lbm as mod
+
+    return mod
+
+
+def test_every_declared_symbol_is_exported(lbm):
+    names = _declared()
+    assert "lbm_step" in names and "lbm_create" in names and len(names) >= 14
+    lib = C.CDLL(lbm.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_default_options(lbm):
+    o = lbm.lbm_default_options()
+    assert o.precision == lbm.LBM_FP64
+    assert list(o.bc) == [0, 0, 0]
+    assert o.visc_exponent == 0.0 and o.rho_ref == 1.0 and abs(o.T_ref - 1 / 3) < 1e-15
+    assert o.deriv_scheme == lbm.LBM_DERIV_UPWIND and list(o.tile) == [0, 0, 0]
+
+
+@pytest.mark.parametrize("args,needle", [
+    ((5, (4, 4, 1), 1.4, 0.7, 0.01), "lattice"),
+    ((2, (4, 4, 2), 1.4, 0.7, 0.01), "D2Q9"),
+    ((3, (0, 4, 4), 1.4, 0.7, 0.01), "dims"),
+    ((3, (4, 4, 4), 1.0, 0.7, 0.01), "gamma"),
+    ((3, (4, 4, 4), 1.4, 0.0, 0.01), "Pr"),
+    ((3, (4, 4, 4), 1.4, 0.7, -1.0), "mu"),
+    ((3, (4, 4, 4), 1.4, 0.7, float("nan")), "mu"),
+])
+def test_create_rejects_bad_arguments(lbm, args, needle):
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(*args)
+    assert e.value.code == lbm.LBM_EINVAL
+    assert needle in str(e.value)
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(precision=7), "precision"),
+    (dict(bc=(0, 2, 0)), "boundary"),
+    (dict(deriv_scheme=3), "derivative"),
+    (dict(T_ref=0.0), "T_ref"),
+    (dict(rho_ref=-1.0), "rho_ref"),
+    (dict(tile=(48, 4, 8)), "tile"),
+])
+def test_create_rejects_bad_options(lbm, kw, needle):
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(3, (8, 8, 8), 1.4, 0.7, 0.01, **kw)
+    assert e.value.code == lbm.LBM_EINVAL
+    assert needle in str(e.value)
+
+
+def test_null_handle_calls_fail_cleanly(lbm):
+    L = lbm.raw()
+    assert L.lbm_destroy(None) == lbm.LBM_OK
+    assert L.lbm_step(None, 1) == lbm.LBM_EINVAL
+    assert L.lbm_set_stream(None, None) == lbm.LBM_EINVAL
+    assert L.lbm_step_count(None) == -1
+    assert L.lbm_state_bytes(None) == 0
+    assert L.lbm_device_copy(None, None, 16, None) == lbm.LBM_EINVAL
