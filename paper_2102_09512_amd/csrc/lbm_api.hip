@@ -65,6 +65,8 @@ void fill_params(Ctx* c) {
   p.nz = (int)c->n[2];
   for (int a = 0; a < 3; ++a) p.bc[a] = c->opt.bc[a];
   p.ps = c->ps;
+  p.ms = c->ms;
+  p.plane = (int)(D == 3 ? c->n[0] * c->n[1] : c->n[0]);
   const int nm = (D == 3) ? p.nz : p.ny;
   p.tiles_x = (p.nx + c->tile.bx - 1) / c->tile.bx;
   p.tiles_y = (D == 3) ? (p.ny + c->tile.by - 1) / c->tile.by : 1;
@@ -154,8 +156,7 @@ int lbm_create(lbm_handle* out, int lattice, const int64_t dims[3], double gamma
     lbm::Tile t{opt.tile[0] ? opt.tile[0] : tile.bx, opt.tile[1] ? opt.tile[1] : tile.by,
                 opt.tile[2] ? opt.tile[2] : tile.chunk};
     if (lattice == LBM_D2Q9 && !opt.tile[1]) t.by = 1;
-    if (!lbm::tile_supported(lattice, opt.precision, t) || t.chunk < 1)
-      return fail(LBM_EINVAL, "lbm_create: launch tile not available");
+    if (!lbm::tile_supported(lattice, opt.precision, t) || t.chunk < 1) return fail(LBM_EINVAL, "lbm_create: launch tile not available");
     tile = t;
   }
 
@@ -166,8 +167,14 @@ int lbm_create(lbm_handle* out, int lattice, const int64_t dims[3], double gamma
   c->precision = opt.precision;
   for (int a = 0; a < 3; ++a) c->n[a] = dims[a];
   c->N = N;
-  // population arrays start 256-element aligned and are staggered by 64 elements
-  c->ps = ((N + 255) / 256) * 256 + 64;
+  // plane-major layout: per march plane, 2Q in-plane arrays; each array is
+  // 64-element aligned and the arrays are staggered by 64 elements
+  {
+    const int64_t plane = lattice == 3 ? dims[0] * dims[1] : dims[0];
+    c->nm = (int)(lattice == 3 ? dims[2] : dims[1]);
+    c->ps = ((plane + 63) / 64) * 64 + 64;
+    c->ms = c->ps * 2 * c->Q;
+  }
   c->gamma = gamma;
   c->Pr = Pr;
   c->mu = mu;
@@ -179,7 +186,7 @@ int lbm_create(lbm_handle* out, int lattice, const int64_t dims[3], double gamma
     return hip_fail(e, "hipGetDevice");
   }
   fill_params(c);
-  const size_t bytes = word_of(c->precision) * (size_t)(2 * c->Q) * (size_t)c->ps;
+  const size_t bytes = word_of(c->precision) * (size_t)c->nm * (size_t)c->ms;
   for (int k = 0; k < 2; ++k) {
     e = hipMalloc(&c->buf[k], bytes);
     if (e != hipSuccess) {
@@ -334,9 +341,11 @@ int lbm_get_state(lbm_handle h, void* buf, size_t bytes, int mem) {
   if (bytes != lbm_state_bytes(h)) return fail(LBM_EINVAL, "lbm_get_state: wrong buffer size");
   int rc = select_device(c);
   if (rc) return rc;
-  const size_t w = word_of(c->precision);
-  HIP_OR_FAIL(hipMemcpy2DAsync(buf, w * c->N, c->buf[c->cur], w * c->ps, w * c->N, 2 * c->Q,
-                               mem == LBM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, c->stream),
+  // pack into the other population buffer (its content is dead between steps), then copy out
+  void* scratch = c->buf[c->cur ^ 1];
+  HIP_OR_FAIL(lbm::launch_pack(*c, c->buf[c->cur], scratch), "pack kernel");
+  HIP_OR_FAIL(hipMemcpyAsync(buf, scratch, bytes, mem == LBM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                             c->stream),
               "copy state");
   if (mem == LBM_HOST) HIP_OR_FAIL(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   return LBM_OK;
@@ -350,10 +359,10 @@ int lbm_set_state(lbm_handle h, const void* buf, size_t bytes, int mem, int64_t 
   if (bytes != lbm_state_bytes(h)) return fail(LBM_EINVAL, "lbm_set_state: wrong buffer size");
   int rc = select_device(c);
   if (rc) return rc;
-  const size_t w = word_of(c->precision);
-  HIP_OR_FAIL(hipMemcpy2DAsync(c->buf[0], w * c->ps, buf, w * c->N, w * c->N, 2 * c->Q,
-                               mem == LBM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, c->stream),
+  HIP_OR_FAIL(hipMemcpyAsync(c->buf[1], buf, bytes, mem == LBM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                             c->stream),
               "copy state");
+  HIP_OR_FAIL(lbm::launch_unpack(*c, c->buf[1], c->buf[0]), "unpack kernel");
   if (mem == LBM_HOST) HIP_OR_FAIL(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   c->cur = 0;
   c->step = step;

@@ -15,7 +15,9 @@ namespace lbm {
 struct StepParams {
   int nx, ny, nz;
   int bc[3];            // LBM_BC_* per axis
-  long long ps;         // elements between consecutive population arrays
+  long long ps;         // elements between the arrays of two consecutive populations of one plane
+  long long ms;         // elements between two consecutive march planes (z for D3Q27, y for D2Q9)
+  int plane;            // nodes per march plane (nx*ny for D3Q27, nx for D2Q9)
   int tiles_x, tiles_y; // in-plane tiles (tiles_y == 1 for D2Q9)
   int chunks, chunk_len;// march-axis chunks (z for D3Q27, y for D2Q9)
   int nblocks;
@@ -37,7 +39,9 @@ struct Ctx {
   int precision = 0;
   int64_t n[3] = {1, 1, 1};
   int64_t N = 0;
-  long long ps = 0;
+  long long ps = 0;       // population stride inside a plane
+  long long ms = 0;       // march-plane stride
+  int nm = 0;             // number of march planes
   int device = 0;
   hipStream_t stream = nullptr;
   double gamma = 1.4, Pr = 0.71, mu = 0.01;
@@ -66,6 +70,9 @@ int diag_blocks(const Ctx& c);
 hipError_t launch_validate(const Ctx& c, const double* rho, const double* u, const double* T, double* partial,
                            int nblocks, double* out);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// Internal population layout <-> the ABI state layout (2Q arrays of N values).
+hipError_t launch_pack(const Ctx& c, const void* pops, void* state);
+hipError_t launch_unpack(const Ctx& c, const void* state, void* pops);
 // Default launch tile for a lattice/precision and whether a tile is available.
 Tile default_tile(int D, int precision, const int64_t n[3]);
 bool tile_supported(int D, int precision, const Tile& t);

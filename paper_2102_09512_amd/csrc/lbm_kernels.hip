@@ -2,8 +2,14 @@
 //
 // Fused stream-and-collide (one launch per time step)
 // ---------------------------------------------------
-// Populations are stored structure-of-arrays: population i of node n at
-// buf[i * ps + n], f first (i < Q) and g after (Q <= i < 2Q), x fastest.
+// Populations are stored plane-major structure-of-arrays: for every plane of
+// the march axis (z for D3Q27, y for D2Q9) the 2Q populations of that plane
+// follow each other, each as one contiguous in-plane array (x fastest):
+//   buf[m * ms + i * ps + p],  p = in-plane node index, f first (i < Q),
+//   g after (Q <= i < 2Q).
+// A work-group that marches over a few planes then touches a few MB of
+// address space instead of 2Q arrays a whole field apart, which keeps the
+// address translation caches warm.
 // Streaming is done by pull: the thread of node x reads population i from
 // x - c_i (wrapped or clamped per axis) and writes the post-collision values
 // at x, so every store of a wavefront is a contiguous 256-byte (FP32) or
@@ -40,6 +46,12 @@ __device__ inline int fix_coord(int k, int n, int bc) {
   return k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
 }
 
+// Element offset of population i of node n (node = x + nx*(y + ny*z)).
+__device__ inline long long pop_offset(const StepParams& p, int i, long long n) {
+  const long long m = n / p.plane;
+  return m * p.ms + (long long)i * p.ps + (n - m * p.plane);
+}
+
 template <typename S>
 struct StoreOf;
 template <>
@@ -55,7 +67,6 @@ __device__ inline NodeConsts node_consts(const StepParams& p) {
   NodeConsts k;
   k.rho0 = p.rho0;
   k.T0 = p.T0;
-  k.rhoE0 = p.rhoE0;
   k.inv_Cv = p.inv_Cv;
   k.Cv = p.Cv;
   k.Pr = p.Pr;
@@ -65,21 +76,53 @@ __device__ inline NodeConsts node_consts(const StepParams& p) {
   return k;
 }
 
-// Pull-load the 2Q populations arriving at a node.  ox[k], oy[k], om[k] are
-// the element offsets of the coordinates (x + k - 1), (y + k - 1),
-// (march + k - 1) after wrap/clamp; the source of population i is x - c_i.
+// Raw buffer access: a wave-uniform resource (base of one march plane), a
+// per-lane 32-bit byte offset (the in-plane node) and a wave-uniform scalar
+// offset (the population), so a load or store needs no per-lane address
+// arithmetic.  Offsets past the resource's size read 0 and drop writes.
+constexpr int kBufferFlags = 0x00020000;  // raw 32-bit data format (gfx9 family)
+
+__device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, long long bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufferFlags);
+}
+
+template <typename S>
+struct Buf;
+template <>
+struct Buf<float> {
+  static __device__ inline float load(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+  }
+  static __device__ inline void store(float v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
+  }
+};
+template <>
+struct Buf<double> {
+  static __device__ inline double load(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+  }
+  static __device__ inline void store(double v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, vo, so, 0);
+  }
+};
+
+// Pull-load the 2Q populations arriving at a node.  rs[k] is the resource of
+// march plane (m + k - 1) after wrap/clamp; lo[j] is the byte offset inside a
+// plane of the in-plane source (y + j/3 - 1, x + j%3 - 1).  Population i of
+// the source x - c_i sits at scalar offset i * ps_bytes of plane 1 - c_m.
 template <int D, typename S, typename R>
-__device__ inline void pull(const S* __restrict__ src, long long ps, const int* ox, const int* oy, const long long* om,
-                            R* f, R* g) {
+__device__ inline void pull(const __amdgpu_buffer_rsrc_t* rs, unsigned ps_bytes, const unsigned* lo, R* f, R* g) {
   constexpr int Q = lat_q(D);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int cx = vx(i);
     const int cy = (D == 3) ? vy(i) : 0;
     const int cm = (D == 3) ? vz(i) : vy(i);
-    const long long off = om[1 - cm] + oy[1 - cy] + ox[1 - cx];
-    f[i] = (R)src[(long long)i * ps + off];
-    g[i] = (R)src[(long long)(i + Q) * ps + off];
+    const unsigned o = lo[(1 - cy) * 3 + (1 - cx)];
+    f[i] = (R)Buf<S>::load(rs[1 - cm], o, (unsigned)i * ps_bytes);
+    g[i] = (R)Buf<S>::load(rs[1 - cm], o, (unsigned)(i + Q) * ps_bytes);
   }
 }
 
@@ -109,7 +152,7 @@ __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src,
   const int n1 = (D == 3) ? p.ny : 1;
   const int nm = (D == 3) ? p.nz : p.ny;
   const int bc0 = p.bc[0], bc1 = p.bc[1], bcm = (D == 3) ? p.bc[2] : p.bc[1];
-  const long long sm = (D == 3) ? (long long)p.nx * p.ny : (long long)p.nx;  // march-axis stride
+  const long long sm = p.ms;  // march-plane stride
   const long long ps = p.ps;
 
   const int t = threadIdx.x;
@@ -158,20 +201,31 @@ __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src,
     hoy[j] = (D == 3) ? fix_coord(hyn + j - 1, n1, bc1) * p.nx : 0;
   }
 
-  auto march_offsets = [&](int m, long long* om) {
+  const unsigned psb = (unsigned)(ps * (long long)sizeof(S));
+  const long long plane_bytes = sm * (long long)sizeof(S);
+  // byte offsets of the 9 in-plane sources of the core and of the halo node
+  unsigned clo[9], hlo[9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    clo[j] = (unsigned)(sizeof(S) * (unsigned)(coy[j / 3] + cox[j % 3]));
+    hlo[j] = (unsigned)(sizeof(S) * (unsigned)(hoy[j / 3] + hox[j % 3]));
+  }
+  auto march_planes = [&](int m, __amdgpu_buffer_rsrc_t* rs) {
     const int mn = fix_coord(m, nm, bcm);
 #pragma unroll
-    for (int j = 0; j < 3; ++j) om[j] = (long long)fix_coord(mn + j - 1, nm, bcm) * sm;
+    for (int j = 0; j < 3; ++j) rs[j] = plane_rsrc(src + (long long)fix_coord(mn + j - 1, nm, bcm) * sm, plane_bytes);
   };
 
   // Post-streaming moments of the halo node at plane m -> LDS buffer.
   auto halo_plane = [&](int m, int buf) {
     if (!has_halo) return;
-    long long om[3];
-    march_offsets(m, om);
+    __amdgpu_buffer_rsrc_t rs[3];
+    march_planes(m, rs);
     R f[Q], g[Q];
-    pull<D, S, R>(src, ps, hox, hoy, om, f, g);
-    const NodeMoments<R> mm = node_moments<D, R>(f, g, k);
+    pull<D, S, R>(rs, psb, hlo, f, g);
+    NodeMoments<R> mm;
+    if constexpr (DEV) mm = node_moments_light<D>(f, g, k);
+    else mm = node_moments<D, R>(f, g, k);
     if (D == 3) {
       if (hslot == 0) lq1[buf][0][t] = anomaly(mm, 1);
       else if (hslot == 1) lq1[buf][BY + 1][t - BX] = anomaly(mm, 1);
@@ -187,17 +241,19 @@ __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src,
   R fa[Q], ga[Q];
   NodeMoments<R> ma;
   {
-    long long om[3];
-    march_offsets(m0 - 1, om);
-    pull<D, S, R>(src, ps, cox, coy, om, fa, ga);
-    const NodeMoments<R> mm = node_moments<D, R>(fa, ga, k);
+    __amdgpu_buffer_rsrc_t rs[3];
+    march_planes(m0 - 1, rs);
+    pull<D, S, R>(rs, psb, clo, fa, ga);
+    NodeMoments<R> mm;
+    if constexpr (DEV) mm = node_moments_light<D>(fa, ga, k);
+    else mm = node_moments<D, R>(fa, ga, k);
     qm_prev = anomaly(mm, D - 1);
   }
   // plane m0: core populations stay in registers, in-plane anomaly to LDS
   {
-    long long om[3];
-    march_offsets(m0, om);
-    pull<D, S, R>(src, ps, cox, coy, om, fa, ga);
+    __amdgpu_buffer_rsrc_t rs[3];
+    march_planes(m0, rs);
+    pull<D, S, R>(rs, psb, clo, fa, ga);
     ma = node_moments<D, R>(fa, ga, k);
     qm_cur = anomaly(ma, D - 1);
     lq0[0][ly][lx + 1] = anomaly(ma, 0);
@@ -212,9 +268,9 @@ __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src,
     R fb[Q], gb[Q];
     NodeMoments<R> mb;
     {
-      long long om[3];
-      march_offsets(m + 1, om);
-      pull<D, S, R>(src, ps, cox, coy, om, fb, gb);
+      __amdgpu_buffer_rsrc_t rs[3];
+      march_planes(m + 1, rs);
+      pull<D, S, R>(rs, psb, clo, fb, gb);
       mb = node_moments<D, R>(fb, gb, k);
       qm_next = anomaly(mb, D - 1);
       lq0[nb][ly][lx + 1] = anomaly(mb, 0);
@@ -233,11 +289,12 @@ __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src,
     }
     collide<D, R, DEV>(fa, ga, ma, dd, k);
     if (active) {
-      const long long node = (long long)cnode + (long long)m * sm;
+      const __amdgpu_buffer_rsrc_t rd = plane_rsrc(dst + (long long)m * sm, plane_bytes);
+      const unsigned o = (unsigned)(sizeof(S) * (unsigned)cnode);
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        dst[(long long)i * ps + node] = (S)fa[i];
-        dst[(long long)(i + Q) * ps + node] = (S)ga[i];
+        Buf<S>::store((S)fa[i], rd, o, (unsigned)i * psb);
+        Buf<S>::store((S)ga[i], rd, o, (unsigned)(i + Q) * psb);
       }
     }
     __syncthreads();
@@ -281,8 +338,8 @@ __global__ void __launch_bounds__(256) init_kernel(const double* __restrict__ rh
   equilibria<D, R, DEV>(m, d, k, fe, ge);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    dst[(long long)i * p.ps + n] = (S)fe[i];
-    dst[(long long)(i + Q) * p.ps + n] = (S)ge[i];
+    dst[pop_offset(p, i, n)] = (S)fe[i];
+    dst[pop_offset(p, i + Q, n)] = (S)ge[i];
   }
 }
 
@@ -300,9 +357,9 @@ __global__ void __launch_bounds__(256) fields_kernel(const S* __restrict__ pops,
   double s0 = 0, jx = 0, jy = 0, jz = 0, se = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const double v = (double)pops[(long long)i * p.ps + n];
+    const double v = (double)pops[pop_offset(p, i, n)];
     s0 += v;
-    se += (double)pops[(long long)(i + Q) * p.ps + n];
+    se += (double)pops[pop_offset(p, i + Q, n)];
     const int cx = vx(i), cy = vy(i), cz = (D == 3) ? vz(i) : 0;
     if (cx) jx += cx > 0 ? v : -v;
     if (cy) jy += cy > 0 ? v : -v;
@@ -444,6 +501,22 @@ __global__ void __launch_bounds__(256) copy_kernel(const float4* __restrict__ sr
     dst[i] = src[i];
 }
 
+template <typename S>
+__global__ void __launch_bounds__(256) pack_kernel(const S* __restrict__ pops, S* __restrict__ state, long long N,
+                                                   int nq, const StepParams p) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  for (int i = 0; i < nq; ++i) state[(long long)i * N + n] = pops[pop_offset(p, i, n)];
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) unpack_kernel(const S* __restrict__ state, S* __restrict__ pops, long long N,
+                                                     int nq, const StepParams p) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  for (int i = 0; i < nq; ++i) pops[pop_offset(p, i, n)] = state[(long long)i * N + n];
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -458,8 +531,10 @@ static hipError_t launch_step_t(const Ctx& c, const void* src, void* dst) {
 // Compiled launch shapes: (D, precision) -> {BX, BY}; the march chunk is a
 // runtime parameter.
 Tile default_tile(int D, int precision, const int64_t n[3]) {
-  (void)precision;
-  if (D == 3) return Tile{64, 4, (int)(n[2] < 32 ? n[2] : 32)};
+  if (D == 3) {
+    if (precision == LBM_FP64) return Tile{64, 8, (int)(n[2] < 32 ? n[2] : 32)};
+    return Tile{64, 8, (int)(n[2] < 64 ? n[2] : 64)};
+  }
   return Tile{128, 1, (int)(n[1] < 32 ? n[1] : 32)};
 }
 
@@ -567,6 +642,32 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) 
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (const float4*)src, (float4*)dst, n16);
+  return hipGetLastError();
+}
+
+}  // namespace lbm
+
+namespace lbm {
+
+hipError_t launch_pack(const Ctx& c, const void* pops, void* state) {
+  const dim3 grid((unsigned)((c.N + 255) / 256)), block(256);
+  if (c.precision == LBM_FP64)
+    hipLaunchKernelGGL(pack_kernel<double>, grid, block, 0, c.stream, (const double*)pops, (double*)state,
+                       (long long)c.N, 2 * c.Q, c.sp);
+  else
+    hipLaunchKernelGGL(pack_kernel<float>, grid, block, 0, c.stream, (const float*)pops, (float*)state,
+                       (long long)c.N, 2 * c.Q, c.sp);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const Ctx& c, const void* state, void* pops) {
+  const dim3 grid((unsigned)((c.N + 255) / 256)), block(256);
+  if (c.precision == LBM_FP64)
+    hipLaunchKernelGGL(unpack_kernel<double>, grid, block, 0, c.stream, (const double*)state, (double*)pops,
+                       (long long)c.N, 2 * c.Q, c.sp);
+  else
+    hipLaunchKernelGGL(unpack_kernel<float>, grid, block, 0, c.stream, (const float*)state, (float*)pops,
+                       (long long)c.N, 2 * c.Q, c.sp);
   return hipGetLastError();
 }
 

@@ -39,8 +39,7 @@ __host__ __device__ constexpr int vx(int i) { return i % 3 - 1; }
 __host__ __device__ constexpr int vy(int i) { return (i / 3) % 3 - 1; }
 __host__ __device__ constexpr int vz(int i) { return (i / 9) % 3 - 1; }
 
-// Moments of one node after streaming, in compute precision R; the
-// conserved sums and T are formed in FP64 first.
+// Moments of one node after streaming, in compute precision R.
 template <typename R>
 struct NodeMoments {
   R rho;     // density
@@ -50,11 +49,10 @@ struct NodeMoments {
   R u[3];
   R pn[6];   // P - P^eq: xx, yy, zz, xy, xz, yz
   R omega, omega1;
-  double s0, j[3], se;  // FP64 sums of the stored values: mass, momentum, energy
 };
 
 struct NodeConsts {
-  double rho0, T0, rhoE0;
+  double rho0, T0;
   double inv_Cv, Cv, Pr;
   double mu0, visc_exp, inv_Tref;
 };
@@ -65,62 +63,95 @@ __device__ inline R viscosity(const NodeConsts& k, R T) {
   return (R)k.mu0 * pow(T * (R)k.inv_Tref, (R)k.visc_exp);
 }
 
-// Streaming has been done by the caller: f, g are the post-streaming
-// populations (deviations when DEV).
+// P - P^eq with P = sum c c f (Eq. (47)) and P^eq = rho T I + rho u u
+// (Eqs. (23), (25)); the isotropic part rho T - rho0 T0 = drho T0 + rho dT.
 template <int D, typename R>
-__device__ inline NodeMoments<R> node_moments(const R* f, const R* g, const NodeConsts& k) {
-  constexpr int Q = lat_q(D);
-  double s0 = 0.0, jx = 0.0, jy = 0.0, jz = 0.0, se = 0.0;
-  R pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const int cx = vx(i), cy = vy(i), cz = (D == 3) ? vz(i) : 0;
-    const double v = (double)f[i];
-    s0 += v;
-    se += (double)g[i];
-    if (cx) jx += cx > 0 ? v : -v;
-    if (cy) jy += cy > 0 ? v : -v;
-    if (cz) jz += cz > 0 ? v : -v;
-    const R w = f[i];
-    if (cx) pxx += w;
-    if (cy) pyy += w;
-    if (cz) pzz += w;
-    if (cx && cy) pxy += (cx == cy) ? w : -w;
-    if (cx && cz) pxz += (cx == cz) ? w : -w;
-    if (cy && cz) pyz += (cy == cz) ? w : -w;
-  }
-  const double rho = k.rho0 + s0;
-  const double ux = jx / rho, uy = jy / rho, uz = (D == 3) ? jz / rho : 0.0;
-  const double E = (k.rhoE0 + se) / rho;
-  const double T = (E - 0.5 * (ux * ux + uy * uy + uz * uz)) * k.inv_Cv;
-  const double dT = T - k.T0;
-
-  NodeMoments<R> m;
-  m.s0 = s0;
-  m.j[0] = jx;
-  m.j[1] = jy;
-  m.j[2] = jz;
-  m.se = se;
-  m.rho = (R)rho;
-  m.drho = (R)s0;
-  m.T = (R)T;
-  m.dT = (R)dT;
-  m.u[0] = (R)ux;
-  m.u[1] = (R)uy;
-  m.u[2] = (R)uz;
-  // P - P^eq with P = sum c c f (Eq. (47)) and P^eq = rho T I + rho u u
-  // (Eqs. (23), (25)); the isotropic part rho T - rho0 T0 = drho T0 + rho dT.
+__device__ inline void nonequilibrium_pressure(NodeMoments<R>& m, const R* p, const NodeConsts& k) {
   const R iso = m.drho * (R)k.T0 + m.rho * m.dT;
-  m.pn[0] = pxx - m.rho * m.u[0] * m.u[0] - iso;
-  m.pn[1] = pyy - m.rho * m.u[1] * m.u[1] - iso;
-  m.pn[2] = (D == 3) ? pzz - m.rho * m.u[2] * m.u[2] - iso : (R)0;
-  m.pn[3] = pxy - m.rho * m.u[0] * m.u[1];
-  m.pn[4] = (D == 3) ? pxz - m.rho * m.u[0] * m.u[2] : (R)0;
-  m.pn[5] = (D == 3) ? pyz - m.rho * m.u[1] * m.u[2] : (R)0;
-  // omega from mu = (1/omega - 1/2) rho T (Eq. (92)); omega_1 from Eq. (96)
+  m.pn[0] = p[0] - m.rho * m.u[0] * m.u[0] - iso;
+  m.pn[1] = p[1] - m.rho * m.u[1] * m.u[1] - iso;
+  m.pn[2] = (D == 3) ? p[2] - m.rho * m.u[2] * m.u[2] - iso : (R)0;
+  m.pn[3] = p[3] - m.rho * m.u[0] * m.u[1];
+  m.pn[4] = (D == 3) ? p[4] - m.rho * m.u[0] * m.u[2] : (R)0;
+  m.pn[5] = (D == 3) ? p[5] - m.rho * m.u[1] * m.u[2] : (R)0;
+}
+
+// omega from mu = (1/omega - 1/2) rho T (Eq. (92)); omega_1 from Eq. (96).
+template <typename R>
+__device__ inline void relaxation_rates(NodeMoments<R>& m, const NodeConsts& k) {
   const R mu = viscosity<R>(k, m.T);
   m.omega = (R)1 / (mu / (m.rho * m.T) + (R)0.5);
   m.omega1 = (R)2 * (R)k.Pr * m.omega / ((R)2 - m.omega + (R)k.Pr * m.omega);
+}
+
+// Moments of the post-streaming populations f, g (Eqs. (3)-(7)); deviations
+// from the rest state (rho0, 0, T0) when the storage is FP32.  FP64 storage
+// (rho0 = 0, rhoE0 = 0) sums the full populations.  The FP32 path keeps
+// every quantity a deviation: rho Cv (T - T0) = sum g - rho |u|^2 / 2 -
+// (rho - rho0) Cv T0, so no large terms cancel.
+template <int D, typename R>
+__device__ inline NodeMoments<R> node_moments(const R* f, const R* g, const NodeConsts& k) {
+  constexpr int Q = lat_q(D);
+  R s0 = 0, jx = 0, jy = 0, jz = 0, se = 0;
+  R p[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int cx = vx(i), cy = vy(i), cz = (D == 3) ? vz(i) : 0;
+    const R w = f[i];
+    s0 += w;
+    se += g[i];
+    if (cx) jx += cx > 0 ? w : -w;
+    if (cy) jy += cy > 0 ? w : -w;
+    if (cz) jz += cz > 0 ? w : -w;
+    if (cx) p[0] += w;
+    if (cy) p[1] += w;
+    if (cz) p[2] += w;
+    if (cx && cy) p[3] += (cx == cy) ? w : -w;
+    if (cx && cz) p[4] += (cx == cz) ? w : -w;
+    if (cy && cz) p[5] += (cy == cz) ? w : -w;
+  }
+  NodeMoments<R> m;
+  m.drho = s0;
+  m.rho = (R)k.rho0 + s0;
+  const R inv = (R)1 / m.rho;
+  m.u[0] = jx * inv;
+  m.u[1] = jy * inv;
+  m.u[2] = (D == 3) ? jz * inv : (R)0;
+  const R ke = (R)0.5 * m.rho * (m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2]);
+  m.dT = (se - ke - m.drho * (R)(k.Cv * k.T0)) * inv * (R)k.inv_Cv;
+  m.T = (R)k.T0 + m.dT;
+  nonequilibrium_pressure<D, R>(m, p, k);
+  relaxation_rates<R>(m, k);
+  return m;
+}
+
+// Density, velocity and temperature only (no P - P^eq, no rates): where
+// nothing but the anomaly is needed (the halo ring and the plane before a
+// march chunk) in the FP32 kernels.
+template <int D>
+__device__ inline NodeMoments<float> node_moments_light(const float* f, const float* g, const NodeConsts& k) {
+  constexpr int Q = lat_q(D);
+  float s0 = 0.f, jx = 0.f, jy = 0.f, jz = 0.f, se = 0.f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int cx = vx(i), cy = vy(i), cz = (D == 3) ? vz(i) : 0;
+    const float v = f[i];
+    s0 += v;
+    se += g[i];
+    if (cx) jx += cx > 0 ? v : -v;
+    if (cy) jy += cy > 0 ? v : -v;
+    if (cz) jz += cz > 0 ? v : -v;
+  }
+  NodeMoments<float> m;
+  m.drho = s0;
+  m.rho = (float)k.rho0 + s0;
+  const float inv = 1.f / m.rho;
+  m.u[0] = jx * inv;
+  m.u[1] = jy * inv;
+  m.u[2] = (D == 3) ? jz * inv : 0.f;
+  const float ke = 0.5f * m.rho * (m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2]);
+  m.dT = (se - ke - s0 * (float)(k.Cv * k.T0)) * inv * (float)k.inv_Cv;
+  m.T = (float)k.T0 + m.dT;
   return m;
 }
 
@@ -300,51 +331,50 @@ __device__ inline void collide(R* f, R* g, const NodeMoments<R>& m, const R* d, 
   dq[1] = m.u[0] * m.pn[3] + m.u[1] * m.pn[1] + (D == 3 ? m.u[2] * m.pn[5] : (R)0) + (R)0.5 * m.u[1] * d[1];
   dq[2] = (D == 3) ? m.u[0] * m.pn[4] + m.u[1] * m.pn[5] + m.u[2] * m.pn[2] + (R)0.5 * m.u[2] * d[2] : (R)0;
   const R half_dw = (R)0.5 * (m.omega - m.omega1);
+  // Sums of the collision increments (DEV only): mass, momentum, energy.
+  R sf = 0, sx = 0, sy = 0, sz = 0, sg = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int cx = vx(i), cy = vy(i), cz = (D == 3) ? vz(i) : 0;
-    f[i] = f[i] + m.omega * (fe[i] - f[i]);
-    R gn = g[i] + m.omega1 * (ge[i] - g[i]);
+    const R df = m.omega * (fe[i] - f[i]);
+    R dg = m.omega1 * (ge[i] - g[i]);
     const int c2 = cx * cx + cy * cy + cz * cz;
     if (c2 == 1) {
       const R cdq = cx ? (cx > 0 ? dq[0] : -dq[0]) : cy ? (cy > 0 ? dq[1] : -dq[1]) : (cz > 0 ? dq[2] : -dq[2]);
-      gn -= half_dw * cdq;
+      dg -= half_dw * cdq;
     }
-    g[i] = gn;
+    f[i] += df;
+    g[i] += dg;
+    if (DEV) {
+      sf += df;
+      sg += dg;
+      if (cx) sx += cx > 0 ? df : -df;
+      if (cy) sy += cy > 0 ? df : -df;
+      if (cz) sz += cz > 0 ? df : -df;
+    }
   }
   if (DEV) {
-    // The relaxation conserves rho, rho u and rho E exactly (Eqs. (3)-(5)),
-    // but in FP32 the equilibria are built from moments rounded to FP32,
-    // whose rounding keeps its sign at a node for many steps and would make
-    // the totals drift.  Restore the FP64 sums of the streamed values: the
-    // momentum residual on the +-e_a pair, then mass on the rest population;
-    // energy on the rest population of g.
+    // The collision conserves rho, rho u and rho E exactly (Eqs. (3)-(5)), so
+    // the increments sum to zero in exact arithmetic.  In FP32 the equilibria
+    // are evaluated with rounding errors that keep their sign from node to
+    // node and step to step, and the totals would drift.  The increments are
+    // small, so their FP32 sums are accurate: take the momentum residual off
+    // the +-e_a pair and the mass and energy residuals off the rest
+    // populations.
     constexpr int rest = (Q - 1) / 2;
-    double sm = 0.0, sx = 0.0, sy = 0.0, sz = 0.0, sg = 0.0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const int cx = vx(i), cy = vy(i), cz = (D == 3) ? vz(i) : 0;
-      const double v = (double)f[i];
-      if (cx) sx += cx > 0 ? v : -v;
-      if (cy) sy += cy > 0 ? v : -v;
-      if (cz) sz += cz > 0 ? v : -v;
-      sg += (double)g[i];
-    }
     constexpr int px = rest + 1, mx = rest - 1, py = rest + 3, my = rest - 3, pz = rest + 9, mz = rest - 9;
-    const R hx = (R)(0.5 * (m.j[0] - sx)), hy = (R)(0.5 * (m.j[1] - sy));
-    f[px] += hx;
-    f[mx] -= hx;
-    f[py] += hy;
-    f[my] -= hy;
+    const R hx = (R)0.5 * sx, hy = (R)0.5 * sy;
+    f[px] -= hx;
+    f[mx] += hx;
+    f[py] -= hy;
+    f[my] += hy;
     if (D == 3) {
-      const R hz = (R)(0.5 * (m.j[2] - sz));
-      f[pz] += hz;
-      f[mz] -= hz;
+      const R hz = (R)0.5 * sz;
+      f[pz] -= hz;
+      f[mz] += hz;
     }
-#pragma unroll
-    for (int i = 0; i < Q; ++i) sm += (double)f[i];
-    f[rest] += (R)(m.s0 - sm);
-    g[rest] += (R)(m.se - sg);
+    f[rest] -= sf;
+    g[rest] -= sg;
   }
 }
 

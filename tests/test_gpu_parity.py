@@ -402,3 +402,37 @@ def test_fp32_turbulence_statistics_2000_steps_within_one_percent():
     relerr = np.abs(stats[lbm.LBM_FP32_DEV] - stats[lbm.LBM_FP64]) / np.abs(stats[lbm.LBM_FP64])
     print("  max relative difference per statistic:", relerr.max(0), flush=True)
     assert relerr.max() < 0.01
+
+
+@pytest.mark.parametrize("tile", [(64, 4, 7), (64, 8, 5), (32, 8, 9), (64, 8, 23), (64, 8, 64)])
+def test_fp32_tiles_match_oracle(tile):
+    """Every launch shape of the FP32 step kernel gives the result within 1e-5
+    of the oracle (ragged tiles, several march chunks, a chunk longer than the
+    march axis, periodic and zero-gradient axes)."""
+    lbm = _lbm()
+    dims = (70, 21, 23)
+    f = I.smooth_random(3, dims, seed=12, u_amp=0.05)
+    f = (f[0], f[1] + 0.1, f[2])  # keep the upwind branches unambiguous
+    kw = dict(mu=0.02, Pr=0.7, visc_exp=0.76, T_ref=0.15, bc=(0, 1, 0))
+    print(f"[gpu case] fp32 tile={tile}", flush=True)
+    h = lbm.lbm_create(3, dims, 1.4, 0.7, 0.02, precision=lbm.LBM_FP32_DEV, bc=kw["bc"], visc_exponent=0.76,
+                       T_ref=0.15, tile=tile)
+    try:
+        lbm.lbm_init_fields(h, *f)
+        lbm.lbm_step(h, 60)
+        out = [np.zeros(a.shape) for a in f]
+        lbm.lbm_moments(h, *out)
+    finally:
+        lbm.lbm_destroy(h)
+    s = run_oracle(3, dims, f, 60, **kw)
+    check_fields(out, s, 1e-5)
+
+
+@pytest.mark.parametrize("tile", [(64, 1, 32), (128, 1, 5), (256, 1, 1)])
+def test_fp32_d2q9_tiles(tile):
+    """Each D2Q9 launch width on the FP32 shock-vortex case, within 1e-5 of the oracle."""
+    rho, u, T, rh = I.shock_vortex(300, 70, r_v=12.0, x_s=150)
+    kw = dict(mu=0.0198, Pr=0.75, bc=(1, 0, 0), T_ref=0.05)
+    out, _, _ = run_gpu(2, (300, 70), (rho, u, T), 80, fp32=True, want_state=False, tile=tile, **kw)
+    s = run_oracle(2, (300, 70), (rho, u, T), 80, **kw)
+    check_fields(out, s, 1e-5)
