@@ -2,27 +2,31 @@
 //
 // Fused stream-and-collide (one launch per time step)
 // ---------------------------------------------------
-// Populations are stored plane-major structure-of-arrays: for every plane of
-// the march axis (z for D3Q27, y for D2Q9) the 2Q populations of that plane
-// follow each other, each as one contiguous in-plane array (x fastest):
-//   buf[m * ms + i * ps + p],  p = in-plane node index, f first (i < Q),
-//   g after (Q <= i < 2Q).
-// A work-group that marches over a few planes then touches a few MB of
-// address space instead of 2Q arrays a whole field apart, which keeps the
-// address translation caches warm.
-// Streaming is done by pull: the thread of node x reads population i from
-// x - c_i (wrapped or clamped per axis) and writes the post-collision values
-// at x, so every store of a wavefront is a contiguous 256-byte (FP32) or
-// 512-byte (FP64) run.
+// Populations are stored plane-major: for every plane of the march axis (z
+// for D3Q27, y for D2Q9) the Q velocity slots of that plane follow each
+// other, each an in-plane array (x fastest) of (f_i, g_i) pairs:
+//   buf[m * ms + i * 2 ps + 2 p + s],  p = in-plane node index,
+//   s = 0 for f_i, 1 for g_i.
+// f_i and g_i of a node stream from the same neighbour, so one 8-byte (FP32)
+// or 16-byte (FP64) access moves both: half the memory instructions of
+// separate arrays, and a wavefront touches a contiguous 512-byte (FP32) or
+// 1-KB (FP64) run per slot.  A work-group that marches over a few planes
+// touches a few MB of address space instead of 2Q arrays a whole field
+// apart, which keeps the address translation caches warm.
+// Streaming is done by pull: the thread of node x reads slot i from x - c_i
+// (wrapped or clamped per axis) and writes the post-collision values at x.
 //
 // The anomaly correction needs, at node x, the post-streaming anomaly Qt_a of
 // the neighbours x +- e_a of the same step.  A work-group owns a BX x BY tile
 // of an in-plane slab and marches along the last axis (z for D3Q27, y for
 // D2Q9) over a chunk of planes:
 //   - each thread keeps its own node's post-streaming populations in
-//     registers from the plane where they are loaded (m + 1) to the plane where
-//     they are collided (m); the neighbours along the march axis are the
-//     same thread's previous and next planes, held in registers;
+//     registers from the plane where they are loaded to the plane where they
+//     are collided; the neighbours along the march axis are the same
+//     thread's previous and next planes, held in registers.  The FP32 kernel
+//     is software-pipelined two planes deep: while plane m collides, the
+//     loads of plane m + 2 are in flight and plane m + 1 (loaded one
+//     iteration earlier) supplies the anomaly along the march axis;
 //   - neighbours inside the plane are exchanged through LDS; a one-node ring
 //     around the tile (the halo) is computed by the first threads of the
 //     group, which pull the halo nodes' populations and form their moments
@@ -46,10 +50,22 @@ __device__ inline int fix_coord(int k, int n, int bc) {
   return k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
 }
 
-// Element offset of population i of node n (node = x + nx*(y + ny*z)).
-__device__ inline long long pop_offset(const StepParams& p, int i, long long n) {
+// fix_coord for -n <= k < 3n without a division (march-plane indices).
+__device__ inline int fix_near(int k, int n, int bc) {
+  if (bc == LBM_BC_PERIODIC) {
+    k = k < 0 ? k + n : k;
+    k = k >= n ? k - n : k;
+    return k >= n ? k - n : k;
+  }
+  return k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
+}
+
+// Element offset of population i (f_i for i < Q, g_{i-Q} for i >= Q) of
+// node n (node = x + nx*(y + ny*z)).
+__device__ inline long long pop_offset(const StepParams& p, int Q, int i, long long n) {
   const long long m = n / p.plane;
-  return m * p.ms + (long long)i * p.ps + (n - m * p.plane);
+  const int slot = i < Q ? i : i - Q;
+  return m * p.ms + (long long)slot * 2 * p.ps + 2 * (n - m * p.plane) + (i < Q ? 0 : 1);
 }
 
 template <typename S>
@@ -81,39 +97,46 @@ __device__ inline NodeConsts node_consts(const StepParams& p) {
 // offset (the population), so a load or store needs no per-lane address
 // arithmetic.  Offsets past the resource's size read 0 and drop writes.
 constexpr int kBufferFlags = 0x00020000;  // raw 32-bit data format (gfx9 family)
+// Cache policy of the step kernel's stores: default.  (Non-temporal stores
+// measured 5% slower in this kernel on gfx950.)
+constexpr int kStorePolicy = 0;
 
 __device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, long long bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufferFlags);
 }
 
+// One (f_i, g_i) pair per access.
 template <typename S>
 struct Buf;
 template <>
 struct Buf<float> {
-  static __device__ inline float load(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+  typedef float pair_t __attribute__((ext_vector_type(2)));
+  static __device__ inline pair_t load(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    return __builtin_bit_cast(pair_t, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
   }
-  static __device__ inline void store(float v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
+  static __device__ inline void store(pair_t v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, vo, so, kStorePolicy);
   }
 };
 template <>
 struct Buf<double> {
-  static __device__ inline double load(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+  typedef double pair_t __attribute__((ext_vector_type(2)));
+  static __device__ inline pair_t load(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    return __builtin_bit_cast(pair_t, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0));
   }
-  static __device__ inline void store(double v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
-    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, vo, so, 0);
+  static __device__ inline void store(pair_t v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V, v), r, vo, so, kStorePolicy);
   }
 };
 
 // Pull-load the 2Q populations arriving at a node.  rs[k] is the resource of
 // march plane (m + k - 1) after wrap/clamp; lo[j] is the byte offset inside a
-// plane of the in-plane source (y + j/3 - 1, x + j%3 - 1).  Population i of
-// the source x - c_i sits at scalar offset i * ps_bytes of plane 1 - c_m.
+// plane of the in-plane source (y + j/3 - 1, x + j%3 - 1).  Slot i of the
+// source x - c_i sits at scalar offset i * slot_bytes of plane 1 - c_m.
 template <int D, typename S, typename R>
-__device__ inline void pull(const __amdgpu_buffer_rsrc_t* rs, unsigned ps_bytes, const unsigned* lo, R* f, R* g) {
+__device__ inline void pull(const __amdgpu_buffer_rsrc_t* rs, unsigned slot_bytes, const unsigned* lo, R* f, R* g) {
   constexpr int Q = lat_q(D);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -121,8 +144,9 @@ __device__ inline void pull(const __amdgpu_buffer_rsrc_t* rs, unsigned ps_bytes,
     const int cy = (D == 3) ? vy(i) : 0;
     const int cm = (D == 3) ? vz(i) : vy(i);
     const unsigned o = lo[(1 - cy) * 3 + (1 - cx)];
-    f[i] = (R)Buf<S>::load(rs[1 - cm], o, (unsigned)i * ps_bytes);
-    g[i] = (R)Buf<S>::load(rs[1 - cm], o, (unsigned)(i + Q) * ps_bytes);
+    const auto v = Buf<S>::load(rs[1 - cm], o, (unsigned)i * slot_bytes);
+    f[i] = (R)v.x;
+    g[i] = (R)v.y;
   }
 }
 
@@ -201,28 +225,28 @@ __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src,
     hoy[j] = (D == 3) ? fix_coord(hyn + j - 1, n1, bc1) * p.nx : 0;
   }
 
-  const unsigned psb = (unsigned)(ps * (long long)sizeof(S));
+  // FP32 with up to 256 threads per group: two planes in flight (see the
+  // header), in up to 512 registers at one wavefront per SIMD.  FP64 needs
+  // twice the registers per population, and 512-thread groups have half the
+  // registers per thread: one plane in flight.
+  constexpr bool PF2 = DEV && BX * BY <= 256;
+  const unsigned slot_bytes = (unsigned)(2 * ps * (long long)sizeof(S));
   const long long plane_bytes = sm * (long long)sizeof(S);
   // byte offsets of the 9 in-plane sources of the core and of the halo node
   unsigned clo[9], hlo[9];
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
-    clo[j] = (unsigned)(sizeof(S) * (unsigned)(coy[j / 3] + cox[j % 3]));
-    hlo[j] = (unsigned)(sizeof(S) * (unsigned)(hoy[j / 3] + hox[j % 3]));
+    clo[j] = (unsigned)(2 * sizeof(S) * (unsigned)(coy[j / 3] + cox[j % 3]));
+    hlo[j] = (unsigned)(2 * sizeof(S) * (unsigned)(hoy[j / 3] + hox[j % 3]));
   }
   auto march_planes = [&](int m, __amdgpu_buffer_rsrc_t* rs) {
-    const int mn = fix_coord(m, nm, bcm);
+    const int mn = fix_near(m, nm, bcm);  // m0 - 1 <= m <= m1 + 1
 #pragma unroll
-    for (int j = 0; j < 3; ++j) rs[j] = plane_rsrc(src + (long long)fix_coord(mn + j - 1, nm, bcm) * sm, plane_bytes);
+    for (int j = 0; j < 3; ++j) rs[j] = plane_rsrc(src + (long long)fix_near(mn + j - 1, nm, bcm) * sm, plane_bytes);
   };
-
-  // Post-streaming moments of the halo node at plane m -> LDS buffer.
-  auto halo_plane = [&](int m, int buf) {
+  // The halo node's anomaly, from its populations, into LDS buffer buf.
+  auto halo_finish = [&](const R* f, const R* g, int buf) {
     if (!has_halo) return;
-    __amdgpu_buffer_rsrc_t rs[3];
-    march_planes(m, rs);
-    R f[Q], g[Q];
-    pull<D, S, R>(rs, psb, hlo, f, g);
     NodeMoments<R> mm;
     if constexpr (DEV) mm = node_moments_light<D>(f, g, k);
     else mm = node_moments<D, R>(f, g, k);
@@ -235,47 +259,71 @@ __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src,
       lq0[buf][0][hslot == 2 ? 0 : BX + 1] = anomaly(mm, 0);
     }
   };
+  // Own node's in-plane anomalies into LDS buffer buf.
+  auto core_publish = [&](const NodeMoments<R>& mm, int buf) {
+    lq0[buf][ly][lx + 1] = anomaly(mm, 0);
+    if (D == 3) lq1[buf][ly + 1][lx] = anomaly(mm, 1);
+  };
 
+  R qm_prev, qm_cur, qm_next;  // anomaly along the march axis at m - 1, m, m + 1
+  R hf[Q], hg[Q];              // halo node populations (in flight for the next plane)
+  R f0[Q], g0[Q], f1[Q], g1[Q], f2[Q], g2[Q];
+  NodeMoments<R> mo0, mo1, mo2;
   // prologue: anomaly along the march axis at plane m0 - 1 (core only)
-  R qm_prev, qm_cur, qm_next;
-  R fa[Q], ga[Q];
-  NodeMoments<R> ma;
   {
     __amdgpu_buffer_rsrc_t rs[3];
     march_planes(m0 - 1, rs);
-    pull<D, S, R>(rs, psb, clo, fa, ga);
+    pull<D, S, R>(rs, slot_bytes, clo, f0, g0);
     NodeMoments<R> mm;
-    if constexpr (DEV) mm = node_moments_light<D>(fa, ga, k);
-    else mm = node_moments<D, R>(fa, ga, k);
+    if constexpr (DEV) mm = node_moments_light<D>(f0, g0, k);
+    else mm = node_moments<D, R>(f0, g0, k);
     qm_prev = anomaly(mm, D - 1);
   }
   // plane m0: core populations stay in registers, in-plane anomaly to LDS
   {
     __amdgpu_buffer_rsrc_t rs[3];
     march_planes(m0, rs);
-    pull<D, S, R>(rs, psb, clo, fa, ga);
-    ma = node_moments<D, R>(fa, ga, k);
-    qm_cur = anomaly(ma, D - 1);
-    lq0[0][ly][lx + 1] = anomaly(ma, 0);
-    if (D == 3) lq1[0][ly + 1][lx] = anomaly(ma, 1);
-    halo_plane(m0, 0);
+    pull<D, S, R>(rs, slot_bytes, clo, f0, g0);
+    if (has_halo) pull<D, S, R>(rs, slot_bytes, hlo, hf, hg);
+    mo0 = node_moments<D, R>(f0, g0, k);
+    qm_cur = anomaly(mo0, D - 1);
+    core_publish(mo0, 0);
+    halo_finish(hf, hg, 0);
+  }
+  if (PF2) {
+    __amdgpu_buffer_rsrc_t rs[3];
+    march_planes(m0 + 1, rs);
+    pull<D, S, R>(rs, slot_bytes, clo, f1, g1);
+    if (has_halo) pull<D, S, R>(rs, slot_bytes, hlo, hf, hg);
   }
   __syncthreads();
 
-  for (int m = m0; m < m1; ++m) {
+  // One plane: collide plane m (fa, ga, ma), finish plane m + 1 (fb, gb, mb),
+  // issue the loads of plane m + 2 into (fc, gc) (PF2) or of plane m + 1
+  // (otherwise).  The three register sets rotate through the unrolled loop.
+  auto plane = [&](int m, R* fa, R* ga, NodeMoments<R>& ma, R* fb, R* gb, NodeMoments<R>& mb, R* fc, R* gc) {
     const int cb = (m - m0) & 1, nb = cb ^ 1;
-    // load plane m + 1 (core and halo), its moments and anomalies
-    R fb[Q], gb[Q];
-    NodeMoments<R> mb;
-    {
+    const bool more = m + 1 < m1;  // plane m + 1 collides in this chunk
+    if (PF2) {
       __amdgpu_buffer_rsrc_t rs[3];
-      march_planes(m + 1, rs);
-      pull<D, S, R>(rs, psb, clo, fb, gb);
+      march_planes(more ? m + 2 : m + 1, rs);
+      if (more) pull<D, S, R>(rs, slot_bytes, clo, fc, gc);
       mb = node_moments<D, R>(fb, gb, k);
       qm_next = anomaly(mb, D - 1);
-      lq0[nb][ly][lx + 1] = anomaly(mb, 0);
-      if (D == 3) lq1[nb][ly + 1][lx] = anomaly(mb, 1);
-      halo_plane(m + 1, nb);
+      core_publish(mb, nb);
+      halo_finish(hf, hg, nb);
+      if (more && has_halo) pull<D, S, R>(rs, slot_bytes, hlo, hf, hg);
+    } else {
+      // one plane in flight: the halo loads follow the core moments, so the
+      // two sets of populations are not live together
+      __amdgpu_buffer_rsrc_t rs[3];
+      march_planes(m + 1, rs);
+      pull<D, S, R>(rs, slot_bytes, clo, fb, gb);
+      mb = node_moments<D, R>(fb, gb, k);
+      qm_next = anomaly(mb, D - 1);
+      core_publish(mb, nb);
+      if (has_halo) pull<D, S, R>(rs, slot_bytes, hlo, hf, hg);
+      halo_finish(hf, hg, nb);
     }
     // collide plane m
     R dd[3];
@@ -290,22 +338,39 @@ __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src,
     collide<D, R, DEV>(fa, ga, ma, dd, k);
     if (active) {
       const __amdgpu_buffer_rsrc_t rd = plane_rsrc(dst + (long long)m * sm, plane_bytes);
-      const unsigned o = (unsigned)(sizeof(S) * (unsigned)cnode);
+      const unsigned o = (unsigned)(2 * sizeof(S) * (unsigned)cnode);
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        Buf<S>::store((S)fa[i], rd, o, (unsigned)i * psb);
-        Buf<S>::store((S)ga[i], rd, o, (unsigned)(i + Q) * psb);
+        typename Buf<S>::pair_t v;
+        v.x = (S)fa[i];
+        v.y = (S)ga[i];
+        Buf<S>::store(v, rd, o, (unsigned)i * slot_bytes);
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      fa[i] = fb[i];
-      ga[i] = gb[i];
-    }
-    ma = mb;
     qm_prev = qm_cur;
     qm_cur = qm_next;
+  };
+
+  if (PF2) {
+    // sets: plane m in 0, m + 1 in 1, m + 2 loads into 2; then rotate
+    for (int m = m0; m < m1; m += 3) {
+      plane(m, f0, g0, mo0, f1, g1, mo1, f2, g2);
+      if (m + 1 >= m1) break;
+      plane(m + 1, f1, g1, mo1, f2, g2, mo2, f0, g0);
+      if (m + 2 >= m1) break;
+      plane(m + 2, f2, g2, mo2, f0, g0, mo0, f1, g1);
+    }
+  } else {
+    for (int m = m0; m < m1; ++m) {
+      plane(m, f0, g0, mo0, f1, g1, mo1, f2, g2);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        f0[i] = f1[i];
+        g0[i] = g1[i];
+      }
+      mo0 = mo1;
+    }
   }
 }
 
@@ -331,15 +396,15 @@ __global__ void __launch_bounds__(256) init_kernel(const double* __restrict__ rh
   m.u[0] = (R)u[n];
   m.u[1] = (R)u[N + n];
   m.u[2] = (D == 3) ? (R)u[2 * N + n] : (R)0;
-  m.omega = (R)1;  // corr = (2 - omega)/(2 rho omega) multiplies d = 0
-  m.omega1 = (R)1;
+  m.omega = m.omega1 = (R)1;  // unused by the equilibria
+  m.corr = (R)0;                // multiplies d = 0
   R d[3] = {0, 0, 0};
   R fe[Q], ge[Q];
   equilibria<D, R, DEV>(m, d, k, fe, ge);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    dst[pop_offset(p, i, n)] = (S)fe[i];
-    dst[pop_offset(p, i + Q, n)] = (S)ge[i];
+    dst[pop_offset(p, Q, i, n)] = (S)fe[i];
+    dst[pop_offset(p, Q, i + Q, n)] = (S)ge[i];
   }
 }
 
@@ -357,9 +422,9 @@ __global__ void __launch_bounds__(256) fields_kernel(const S* __restrict__ pops,
   double s0 = 0, jx = 0, jy = 0, jz = 0, se = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const double v = (double)pops[pop_offset(p, i, n)];
+    const double v = (double)pops[pop_offset(p, Q, i, n)];
     s0 += v;
-    se += (double)pops[pop_offset(p, i + Q, n)];
+    se += (double)pops[pop_offset(p, Q, i + Q, n)];
     const int cx = vx(i), cy = vy(i), cz = (D == 3) ? vz(i) : 0;
     if (cx) jx += cx > 0 ? v : -v;
     if (cy) jy += cy > 0 ? v : -v;
@@ -497,8 +562,8 @@ __global__ void __launch_bounds__(256) validate_kernel(const double* __restrict_
 
 __global__ void __launch_bounds__(256) copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst,
                                                    long long n16) {
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (long long)gridDim.x * blockDim.x)
-    dst[i] = src[i];
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n16) dst[i] = src[i];
 }
 
 template <typename S>
@@ -506,7 +571,7 @@ __global__ void __launch_bounds__(256) pack_kernel(const S* __restrict__ pops, S
                                                    int nq, const StepParams p) {
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
-  for (int i = 0; i < nq; ++i) state[(long long)i * N + n] = pops[pop_offset(p, i, n)];
+  for (int i = 0; i < nq; ++i) state[(long long)i * N + n] = pops[pop_offset(p, nq / 2, i, n)];
 }
 
 template <typename S>
@@ -514,7 +579,7 @@ __global__ void __launch_bounds__(256) unpack_kernel(const S* __restrict__ state
                                                      int nq, const StepParams p) {
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
-  for (int i = 0; i < nq; ++i) pops[pop_offset(p, i, n)] = state[(long long)i * N + n];
+  for (int i = 0; i < nq; ++i) pops[pop_offset(p, nq / 2, i, n)] = state[(long long)i * N + n];
 }
 
 // ---------------------------------------------------------------------------
@@ -532,8 +597,13 @@ static hipError_t launch_step_t(const Ctx& c, const void* src, void* dst) {
 // runtime parameter.
 Tile default_tile(int D, int precision, const int64_t n[3]) {
   if (D == 3) {
-    if (precision == LBM_FP64) return Tile{64, 8, (int)(n[2] < 32 ? n[2] : 32)};
-    return Tile{64, 8, (int)(n[2] < 64 ? n[2] : 64)};
+    // 64 x 4 tiles, one wavefront per SIMD.  March chunks as long as
+    // possible (fewer prologue planes) while the launch keeps at least one
+    // work-group per compute unit (256).
+    const int64_t tiles = ((n[0] + 63) / 64) * ((n[1] + 3) / 4);
+    int64_t chunk = n[2] * tiles / 256;
+    chunk = chunk < 16 ? 16 : (chunk > 256 ? 256 : chunk);
+    return Tile{64, 4, (int)(chunk < n[2] ? chunk : n[2])};
   }
   return Tile{128, 1, (int)(n[1] < 32 ? n[1] : 32)};
 }
@@ -637,11 +707,14 @@ hipError_t launch_validate(const Ctx& c, const double* rho, const double* u, con
 }
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  // one 16-byte vector per thread; launches of at most 2^30 vectors
   const long long n16 = (long long)(bytes / 16);
-  long long blocks = (n16 + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (const float4*)src, (float4*)dst, n16);
+  constexpr long long kMax = 1LL << 30;
+  for (long long off = 0; off < n16; off += kMax) {
+    const long long n = n16 - off < kMax ? n16 - off : kMax;
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (const float4*)src + off,
+                       (float4*)dst + off, n);
+  }
   return hipGetLastError();
 }
 

@@ -48,7 +48,9 @@ struct NodeMoments {
   R dT;      // T - T0
   R u[3];
   R pn[6];   // P - P^eq: xx, yy, zz, xy, xz, yz
+  R irho;    // 1 / rho
   R omega, omega1;
+  R corr;    // (2 - omega) / (2 rho omega), the factor of d_a in P^ex (Eq. (30))
 };
 
 struct NodeConsts {
@@ -57,10 +59,19 @@ struct NodeConsts {
   double mu0, visc_exp, inv_Tref;
 };
 
-template <typename R>
-__device__ inline R viscosity(const NodeConsts& k, R T) {
-  if (k.visc_exp == 0.0) return (R)k.mu0;
-  return (R)k.mu0 * pow(T * (R)k.inv_Tref, (R)k.visc_exp);
+// Reciprocal: the hardware approximation (about 1 ulp) in FP32, IEEE
+// division in FP64.
+__device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double recip(double x) { return 1.0 / x; }
+
+// mu = mu0 (T / T_ref)^n; FP32 through the hardware log2 / exp2.
+__device__ inline double viscosity(const NodeConsts& k, double T) {
+  if (k.visc_exp == 0.0) return k.mu0;
+  return k.mu0 * pow(T * k.inv_Tref, k.visc_exp);
+}
+__device__ inline float viscosity(const NodeConsts& k, float T) {
+  if (k.visc_exp == 0.0) return (float)k.mu0;
+  return (float)k.mu0 * __builtin_amdgcn_exp2f((float)k.visc_exp * __builtin_amdgcn_logf(T * (float)k.inv_Tref));
 }
 
 // P - P^eq with P = sum c c f (Eq. (47)) and P^eq = rho T I + rho u u
@@ -76,12 +87,96 @@ __device__ inline void nonequilibrium_pressure(NodeMoments<R>& m, const R* p, co
   m.pn[5] = (D == 3) ? p[5] - m.rho * m.u[1] * m.u[2] : (R)0;
 }
 
-// omega from mu = (1/omega - 1/2) rho T (Eq. (92)); omega_1 from Eq. (96).
+// omega from mu = (1/omega - 1/2) rho T (Eq. (92)): 1/omega = nu + 1/2 with
+// nu = mu / (rho T).  Eq. (96) then reduces to 1/omega_1 = nu / Pr + 1/2, and
+// the factor (2 - omega) / (2 rho omega) of Eq. (30) to nu / rho.
 template <typename R>
 __device__ inline void relaxation_rates(NodeMoments<R>& m, const NodeConsts& k) {
-  const R mu = viscosity<R>(k, m.T);
-  m.omega = (R)1 / (mu / (m.rho * m.T) + (R)0.5);
-  m.omega1 = (R)2 * (R)k.Pr * m.omega / ((R)2 - m.omega + (R)k.Pr * m.omega);
+  const R mu = viscosity(k, m.T);
+  const R nu = mu * recip(m.rho * m.T);
+  m.omega = recip(nu + (R)0.5);
+  m.omega1 = recip(nu * (R)(1.0 / k.Pr) + (R)0.5);
+  m.corr = nu * m.irho;
+}
+
+// Zeroth, first and second moments of one population set (Eqs. (3), (4),
+// (47)), summed row by row: for each (c_y, c_z) the three x-neighbours are
+// combined first, then the rows.  s[0] = sum f, j[a] = sum c_a f,
+// p = (xx, yy, zz, xy, xz, yz) of sum c c f.
+template <int D, typename R>
+__device__ inline void moment_sums(const R* f, R& s, R* j, R* p) {
+  if constexpr (sizeof(R) == 8) {
+    // FP64: one pass in population order (fewer live registers)
+    constexpr int Q = lat_q(D);
+    s = 0;
+    j[0] = j[1] = j[2] = 0;
+    p[0] = p[1] = p[2] = p[3] = p[4] = p[5] = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int cx = vx(i), cy = vy(i), cz = (D == 3) ? vz(i) : 0;
+      const R w = f[i];
+      s += w;
+      if (cx) j[0] += cx > 0 ? w : -w;
+      if (cy) j[1] += cy > 0 ? w : -w;
+      if (cz) j[2] += cz > 0 ? w : -w;
+      if (cx) p[0] += w;
+      if (cy) p[1] += w;
+      if (cz) p[2] += w;
+      if (cx && cy) p[3] += (cx == cy) ? w : -w;
+      if (cx && cz) p[4] += (cx == cz) ? w : -w;
+      if (cy && cz) p[5] += (cy == cz) ? w : -w;
+    }
+    return;
+  }
+  constexpr int NR = (D == 3) ? 9 : 3;  // rows: index jy + 3 jz, jy = c_y + 1, jz = c_z + 1
+  R r0[NR], rx[NR], rxx[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    rxx[r] = f[3 * r + 2] + f[3 * r];
+    rx[r] = f[3 * r + 2] - f[3 * r];
+    r0[r] = rxx[r] + f[3 * r + 1];
+  }
+  if (D == 3) {
+    R l0[3], lx[3], lxx[3];  // per z layer
+#pragma unroll
+    for (int z = 0; z < 3; ++z) {
+      l0[z] = (r0[3 * z] + r0[3 * z + 2]) + r0[3 * z + 1];
+      lx[z] = (rx[3 * z] + rx[3 * z + 2]) + rx[3 * z + 1];
+      lxx[z] = (rxx[3 * z] + rxx[3 * z + 2]) + rxx[3 * z + 1];
+    }
+    s = (l0[0] + l0[2]) + l0[1];
+    j[0] = (lx[0] + lx[2]) + lx[1];
+    p[0] = (lxx[0] + lxx[2]) + lxx[1];
+    j[1] = ((r0[2] - r0[0]) + (r0[8] - r0[6])) + (r0[5] - r0[3]);
+    p[1] = ((r0[2] + r0[0]) + (r0[8] + r0[6])) + (r0[5] + r0[3]);
+    j[2] = l0[2] - l0[0];
+    p[2] = l0[2] + l0[0];
+    p[3] = ((rx[2] - rx[0]) + (rx[8] - rx[6])) + (rx[5] - rx[3]);
+    p[4] = lx[2] - lx[0];
+    p[5] = (r0[8] + r0[0]) - (r0[6] + r0[2]);
+  } else {
+    s = (r0[0] + r0[2]) + r0[1];
+    j[0] = (rx[0] + rx[2]) + rx[1];
+    p[0] = (rxx[0] + rxx[2]) + rxx[1];
+    j[1] = r0[2] - r0[0];
+    p[1] = r0[2] + r0[0];
+    p[3] = rx[2] - rx[0];
+    j[2] = p[2] = p[4] = p[5] = (R)0;
+  }
+}
+
+// Plain sum of Q values, three at a time then rows.
+template <int D, typename R>
+__device__ inline R total(const R* g) {
+  constexpr int NR = (D == 3) ? 9 : 3;
+  R r[NR];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) r[i] = (g[3 * i] + g[3 * i + 2]) + g[3 * i + 1];
+  if (D == 3) {
+    const R l0 = (r[0] + r[2]) + r[1], l1 = (r[3] + r[5]) + r[4], l2 = (r[6] + r[8]) + r[7];
+    return (l0 + l2) + l1;
+  }
+  return (r[0] + r[2]) + r[1];
 }
 
 // Moments of the post-streaming populations f, g (Eqs. (3)-(7)); deviations
@@ -91,34 +186,18 @@ __device__ inline void relaxation_rates(NodeMoments<R>& m, const NodeConsts& k) 
 // (rho - rho0) Cv T0, so no large terms cancel.
 template <int D, typename R>
 __device__ inline NodeMoments<R> node_moments(const R* f, const R* g, const NodeConsts& k) {
-  constexpr int Q = lat_q(D);
-  R s0 = 0, jx = 0, jy = 0, jz = 0, se = 0;
-  R p[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const int cx = vx(i), cy = vy(i), cz = (D == 3) ? vz(i) : 0;
-    const R w = f[i];
-    s0 += w;
-    se += g[i];
-    if (cx) jx += cx > 0 ? w : -w;
-    if (cy) jy += cy > 0 ? w : -w;
-    if (cz) jz += cz > 0 ? w : -w;
-    if (cx) p[0] += w;
-    if (cy) p[1] += w;
-    if (cz) p[2] += w;
-    if (cx && cy) p[3] += (cx == cy) ? w : -w;
-    if (cx && cz) p[4] += (cx == cz) ? w : -w;
-    if (cy && cz) p[5] += (cy == cz) ? w : -w;
-  }
+  R s0, j[3], p[6];
+  moment_sums<D, R>(f, s0, j, p);
+  const R se = total<D, R>(g);
   NodeMoments<R> m;
   m.drho = s0;
   m.rho = (R)k.rho0 + s0;
-  const R inv = (R)1 / m.rho;
-  m.u[0] = jx * inv;
-  m.u[1] = jy * inv;
-  m.u[2] = (D == 3) ? jz * inv : (R)0;
+  m.irho = recip(m.rho);
+  m.u[0] = j[0] * m.irho;
+  m.u[1] = j[1] * m.irho;
+  m.u[2] = (D == 3) ? j[2] * m.irho : (R)0;
   const R ke = (R)0.5 * m.rho * (m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2]);
-  m.dT = (se - ke - m.drho * (R)(k.Cv * k.T0)) * inv * (R)k.inv_Cv;
+  m.dT = (se - ke - m.drho * (R)(k.Cv * k.T0)) * m.irho * (R)k.inv_Cv;
   m.T = (R)k.T0 + m.dT;
   nonequilibrium_pressure<D, R>(m, p, k);
   relaxation_rates<R>(m, k);
@@ -130,27 +209,40 @@ __device__ inline NodeMoments<R> node_moments(const R* f, const R* g, const Node
 // march chunk) in the FP32 kernels.
 template <int D>
 __device__ inline NodeMoments<float> node_moments_light(const float* f, const float* g, const NodeConsts& k) {
-  constexpr int Q = lat_q(D);
-  float s0 = 0.f, jx = 0.f, jy = 0.f, jz = 0.f, se = 0.f;
+  constexpr int NR = (D == 3) ? 9 : 3;
+  float r0[NR], rx[NR];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const int cx = vx(i), cy = vy(i), cz = (D == 3) ? vz(i) : 0;
-    const float v = f[i];
-    s0 += v;
-    se += g[i];
-    if (cx) jx += cx > 0 ? v : -v;
-    if (cy) jy += cy > 0 ? v : -v;
-    if (cz) jz += cz > 0 ? v : -v;
+  for (int r = 0; r < NR; ++r) {
+    rx[r] = f[3 * r + 2] - f[3 * r];
+    r0[r] = (f[3 * r + 2] + f[3 * r]) + f[3 * r + 1];
   }
+  float s0, jx, jy, jz = 0.f;
+  if (D == 3) {
+    float l0[3], lx[3];
+#pragma unroll
+    for (int z = 0; z < 3; ++z) {
+      l0[z] = (r0[3 * z] + r0[3 * z + 2]) + r0[3 * z + 1];
+      lx[z] = (rx[3 * z] + rx[3 * z + 2]) + rx[3 * z + 1];
+    }
+    s0 = (l0[0] + l0[2]) + l0[1];
+    jx = (lx[0] + lx[2]) + lx[1];
+    jy = ((r0[2] - r0[0]) + (r0[8] - r0[6])) + (r0[5] - r0[3]);
+    jz = l0[2] - l0[0];
+  } else {
+    s0 = (r0[0] + r0[2]) + r0[1];
+    jx = (rx[0] + rx[2]) + rx[1];
+    jy = r0[2] - r0[0];
+  }
+  const float se = total<D, float>(g);
   NodeMoments<float> m;
   m.drho = s0;
   m.rho = (float)k.rho0 + s0;
-  const float inv = 1.f / m.rho;
-  m.u[0] = jx * inv;
-  m.u[1] = jy * inv;
-  m.u[2] = (D == 3) ? jz * inv : 0.f;
+  m.irho = recip(m.rho);
+  m.u[0] = jx * m.irho;
+  m.u[1] = jy * m.irho;
+  m.u[2] = jz * m.irho;
   const float ke = 0.5f * m.rho * (m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2]);
-  m.dT = (se - ke - s0 * (float)(k.Cv * k.T0)) * inv * (float)k.inv_Cv;
+  m.dT = (se - ke - s0 * (float)(k.Cv * k.T0)) * m.irho * (float)k.inv_Cv;
   m.T = (float)k.T0 + m.dT;
   return m;
 }
@@ -253,7 +345,7 @@ template <int D, typename R, bool DEV>
 __device__ inline void equilibria(const NodeMoments<R>& m, const R* d, const NodeConsts& k, R* fe, R* ge) {
   const R T0 = (R)k.T0, rho0 = (R)k.rho0;
   const Rest<R> rs = rest_factors<R>(T0);
-  const R corr = ((R)2 - m.omega) / ((R)2 * m.rho * m.omega);
+  const R corr = m.corr;
 
   AxisF<R> F[3];
   AxisG<R> G[3];
@@ -331,26 +423,52 @@ __device__ inline void collide(R* f, R* g, const NodeMoments<R>& m, const R* d, 
   dq[1] = m.u[0] * m.pn[3] + m.u[1] * m.pn[1] + (D == 3 ? m.u[2] * m.pn[5] : (R)0) + (R)0.5 * m.u[1] * d[1];
   dq[2] = (D == 3) ? m.u[0] * m.pn[4] + m.u[1] * m.pn[5] + m.u[2] * m.pn[2] + (R)0.5 * m.u[2] * d[2] : (R)0;
   const R half_dw = (R)0.5 * (m.omega - m.omega1);
-  // Sums of the collision increments (DEV only): mass, momentum, energy.
-  R sf = 0, sx = 0, sy = 0, sz = 0, sg = 0;
+  // Row sums of the collision increments (DEV only), rows as in moment_sums.
+  constexpr int NR = (D == 3) ? 9 : 3;
+  R r0[NR], rx[NR], rg[NR];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const int cx = vx(i), cy = vy(i), cz = (D == 3) ? vz(i) : 0;
-    const R df = m.omega * (fe[i] - f[i]);
-    R dg = m.omega1 * (ge[i] - g[i]);
-    const int c2 = cx * cx + cy * cy + cz * cz;
-    if (c2 == 1) {
-      const R cdq = cx ? (cx > 0 ? dq[0] : -dq[0]) : cy ? (cy > 0 ? dq[1] : -dq[1]) : (cz > 0 ? dq[2] : -dq[2]);
-      dg -= half_dw * cdq;
+  for (int r = 0; r < NR; ++r) {
+    R df[3], dg[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int i = 3 * r + c;
+      const int cx = vx(i), cy = vy(i), cz = (D == 3) ? vz(i) : 0;
+      df[c] = m.omega * (fe[i] - f[i]);
+      dg[c] = m.omega1 * (ge[i] - g[i]);
+      const int c2 = cx * cx + cy * cy + cz * cz;
+      if (c2 == 1) {
+        const R cdq = cx ? (cx > 0 ? dq[0] : -dq[0]) : cy ? (cy > 0 ? dq[1] : -dq[1]) : (cz > 0 ? dq[2] : -dq[2]);
+        dg[c] -= half_dw * cdq;
+      }
+      f[i] += df[c];
+      g[i] += dg[c];
     }
-    f[i] += df;
-    g[i] += dg;
     if (DEV) {
-      sf += df;
-      sg += dg;
-      if (cx) sx += cx > 0 ? df : -df;
-      if (cy) sy += cy > 0 ? df : -df;
-      if (cz) sz += cz > 0 ? df : -df;
+      rx[r] = df[2] - df[0];
+      r0[r] = (df[2] + df[0]) + df[1];
+      rg[r] = (dg[2] + dg[0]) + dg[1];
+    }
+  }
+  R sf = 0, sx = 0, sy = 0, sz = 0, sg = 0;
+  if (DEV) {
+    if (D == 3) {
+      R l0[3], lx[3], lg[3];
+#pragma unroll
+      for (int z = 0; z < 3; ++z) {
+        l0[z] = (r0[3 * z] + r0[3 * z + 2]) + r0[3 * z + 1];
+        lx[z] = (rx[3 * z] + rx[3 * z + 2]) + rx[3 * z + 1];
+        lg[z] = (rg[3 * z] + rg[3 * z + 2]) + rg[3 * z + 1];
+      }
+      sf = (l0[0] + l0[2]) + l0[1];
+      sx = (lx[0] + lx[2]) + lx[1];
+      sg = (lg[0] + lg[2]) + lg[1];
+      sy = ((r0[2] - r0[0]) + (r0[8] - r0[6])) + (r0[5] - r0[3]);
+      sz = l0[2] - l0[0];
+    } else {
+      sf = (r0[0] + r0[2]) + r0[1];
+      sx = (rx[0] + rx[2]) + rx[1];
+      sg = (rg[0] + rg[2]) + rg[1];
+      sy = r0[2] - r0[0];
     }
   }
   if (DEV) {
