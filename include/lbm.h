@@ -44,9 +44,13 @@ typedef struct lbm_ctx* lbm_handle;
 /* Lattices: value = D.  D3Q27 is Eq. (8); D2Q9 drops the z factor of the
    product form (Eq. (12)). */
 enum { LBM_D2Q9 = 2, LBM_D3Q27 = 3 };
-/* Population storage.  LBM_FP32_DEV stores f_i - f^eq_i(rho_ref, 0, T_ref)
-   and g_i - g^eq_i(rho_ref, 0, T_ref) in FP32 and collides in FP32; mass,
-   momentum and energy sums and the temperature recovery are FP64. */
+/* Population storage.  LBM_FP32_DEV stores f_i - f^eq_i(rho_ref, u_ref, T_ref)
+   and g_i - g^eq_i(rho_ref, u_ref, T_ref) in FP32 and collides in FP32 with
+   every quantity in deviation form from that reference state; the collision
+   restores its FP32 mass, momentum and energy residuals, and moments and
+   diagnostics are FP64.  The reference should be close to the flow's typical
+   state (e.g. the free stream): the storage error scales with the size of
+   the deviations. */
 enum { LBM_FP64 = 0, LBM_FP32_DEV = 1 };
 /* Boundaries, per axis (both ends): periodic wrap, or zero-gradient (the
    streaming source and every difference neighbour are clamped to the domain). */
@@ -69,10 +73,11 @@ typedef struct {
   int precision;        /* LBM_FP64 (default) or LBM_FP32_DEV */
   int bc[3];            /* per axis; default LBM_BC_PERIODIC */
   double visc_exponent; /* mu = mu0 (T/T_ref)^visc_exponent (Sec. III.D); 0 = constant mu (default) */
-  double T_ref;         /* T_0 of the power law and rest temperature of FP32 deviations; default 1/3 */
-  double rho_ref;       /* rest density of FP32 deviations; default 1 */
+  double T_ref;         /* T_0 of the power law and reference temperature of FP32 deviations; default 1/3 */
+  double rho_ref;       /* reference density of FP32 deviations; default 1 */
   int deriv_scheme;     /* LBM_DERIV_UPWIND (default) or LBM_DERIV_CENTRAL */
   int tile[3];          /* launch shape of the step kernel: x width, y width (D3Q27), march chunk; 0 = default */
+  double u_ref[3];      /* reference velocity of FP32 deviations (|u_ref_a| < 1); default 0 */
 } lbm_options;
 
 /* Fills *opt with the defaults above. */

@@ -91,9 +91,41 @@ void fill_params(Ctx* c) {
     p.inv_Cv = 1.0 / p.Cv;
     p.rho0 = (double)(float)c->opt.rho_ref;
     p.T0 = (double)(float)c->opt.T_ref;
-    p.rhoE0 = p.rho0 * p.Cv * p.T0;  // sum_i g^eq_i(rho0, 0, T0) = rho0 C_v T0
+    double u2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double u0 = a < D ? (double)(float)c->opt.u_ref[a] : 0.0;
+      p.u0[a] = u0;
+      p.j0[a] = p.rho0 * u0;
+      u2 += u0 * u0;
+      // product-form factors of the reference populations along axis a:
+      // f-factors Psi_c(u0, P0) (equal to the a-factors of g^eq) and the
+      // b-factors of g^eq at (u0, T0)
+      const double P0 = p.T0 + u0 * u0;
+      const double B1 = 0.5 * u0 * (u0 * u0 + 2.0 * p.T0);
+      const double B2 = 0.5 * (u0 * u0 * u0 * u0 + 5.0 * u0 * u0 * p.T0 + 2.0 * p.T0 * p.T0);
+      p.P0[a] = P0;
+      p.psi0[a][0] = 0.5 * (-u0 + P0);
+      p.psi0[a][1] = 1.0 - P0;
+      p.psi0[a][2] = 0.5 * (u0 + P0);
+      p.b0[a][0] = 0.5 * (-B1 + B2);
+      p.b0[a][1] = 0.5 * u0 * u0 - B2;
+      p.b0[a][2] = 0.5 * (B1 + B2);
+    }
+    p.rhoE0 = p.rho0 * (p.Cv * p.T0 + 0.5 * u2);  // sum_i g_i of the reference
   } else {
     p.rho0 = p.T0 = p.rhoE0 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      p.u0[a] = p.j0[a] = p.P0[a] = 0.0;
+      for (int c = 0; c < 3; ++c) p.psi0[a][c] = p.b0[a][c] = 0.0;
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    p.u0f[a] = (float)p.u0[a];
+    p.P0f[a] = (float)p.P0[a];
+    for (int c = 0; c < 3; ++c) {
+      p.psi0f[a][c] = (float)p.psi0[a][c];
+      p.b0f[a][c] = (float)p.b0[a][c];
+    }
   }
 }
 
@@ -148,6 +180,9 @@ int lbm_create(lbm_handle* out, int lattice, const int64_t dims[3], double gamma
   if (!std::isfinite(opt.visc_exponent)) return fail(LBM_EINVAL, "lbm_create: bad viscosity exponent");
   if (!(opt.T_ref > 0.0) || !std::isfinite(opt.T_ref)) return fail(LBM_EINVAL, "lbm_create: T_ref must be > 0");
   if (!(opt.rho_ref > 0.0) || !std::isfinite(opt.rho_ref)) return fail(LBM_EINVAL, "lbm_create: rho_ref must be > 0");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(opt.u_ref[a]) || std::fabs(opt.u_ref[a]) >= 1.0)
+      return fail(LBM_EINVAL, "lbm_create: u_ref components must be finite and |u_ref| < 1");
   const int64_t N = dims[0] * dims[1] * dims[2];
   if (N > ((int64_t)1 << 31) - 1024) return fail(LBM_EINVAL, "lbm_create: more than 2^31 nodes");
 

@@ -22,7 +22,13 @@ struct StepParams {
   int chunks, chunk_len;// march-axis chunks (z for D3Q27, y for D2Q9)
   int nblocks;
   int deriv;            // LBM_DERIV_*
-  double rho0, T0, rhoE0;   // rest state of the deviation storage (all 0 for FP64 storage)
+  // Reference state (rho0, u0, T0) of the FP32 deviation storage; all zero
+  // for FP64 storage.  rhoE0 = rho0 (Cv T0 + |u0|^2/2) and j0 = rho0 u0 are
+  // the reference's energy and momentum; P0, psi0, b0 the per-axis factors
+  // of its product-form populations (see NodeConsts).
+  double rho0, T0, rhoE0;
+  double u0[3], j0[3], P0[3], psi0[3][3], b0[3][3];
+  float u0f[3], P0f[3], psi0f[3][3], b0f[3][3];
   double Cv, inv_Cv, Pr;
   double mu0, visc_exp, inv_Tref;
   double gamma;

@@ -89,6 +89,18 @@ __device__ inline NodeConsts node_consts(const StepParams& p) {
   k.mu0 = p.mu0;
   k.visc_exp = p.visc_exp;
   k.inv_Tref = p.inv_Tref;
+  for (int a = 0; a < 3; ++a) {
+    k.u0[a] = p.u0[a];
+    k.P0[a] = p.P0[a];
+    k.u0f[a] = p.u0f[a];
+    k.P0f[a] = p.P0f[a];
+    for (int c = 0; c < 3; ++c) {
+      k.psi0[a][c] = p.psi0[a][c];
+      k.b0[a][c] = p.b0[a][c];
+      k.psi0f[a][c] = p.psi0f[a][c];
+      k.b0f[a][c] = p.b0f[a][c];
+    }
+  }
   return k;
 }
 
@@ -251,18 +263,18 @@ __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src,
     if constexpr (DEV) mm = node_moments_light<D>(f, g, k);
     else mm = node_moments<D, R>(f, g, k);
     if (D == 3) {
-      if (hslot == 0) lq1[buf][0][t] = anomaly(mm, 1);
-      else if (hslot == 1) lq1[buf][BY + 1][t - BX] = anomaly(mm, 1);
-      else if (hslot == 2) lq0[buf][t - 2 * BX][0] = anomaly(mm, 0);
-      else lq0[buf][t - 2 * BX - BY][BX + 1] = anomaly(mm, 0);
+      if (hslot == 0) lq1[buf][0][t] = anomaly(mm, 1, k);
+      else if (hslot == 1) lq1[buf][BY + 1][t - BX] = anomaly(mm, 1, k);
+      else if (hslot == 2) lq0[buf][t - 2 * BX][0] = anomaly(mm, 0, k);
+      else lq0[buf][t - 2 * BX - BY][BX + 1] = anomaly(mm, 0, k);
     } else {
-      lq0[buf][0][hslot == 2 ? 0 : BX + 1] = anomaly(mm, 0);
+      lq0[buf][0][hslot == 2 ? 0 : BX + 1] = anomaly(mm, 0, k);
     }
   };
   // Own node's in-plane anomalies into LDS buffer buf.
   auto core_publish = [&](const NodeMoments<R>& mm, int buf) {
-    lq0[buf][ly][lx + 1] = anomaly(mm, 0);
-    if (D == 3) lq1[buf][ly + 1][lx] = anomaly(mm, 1);
+    lq0[buf][ly][lx + 1] = anomaly(mm, 0, k);
+    if (D == 3) lq1[buf][ly + 1][lx] = anomaly(mm, 1, k);
   };
 
   R qm_prev, qm_cur, qm_next;  // anomaly along the march axis at m - 1, m, m + 1
@@ -277,7 +289,7 @@ __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src,
     NodeMoments<R> mm;
     if constexpr (DEV) mm = node_moments_light<D>(f0, g0, k);
     else mm = node_moments<D, R>(f0, g0, k);
-    qm_prev = anomaly(mm, D - 1);
+    qm_prev = anomaly(mm, D - 1, k);
   }
   // plane m0: core populations stay in registers, in-plane anomaly to LDS
   {
@@ -286,7 +298,7 @@ __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src,
     pull<D, S, R>(rs, slot_bytes, clo, f0, g0);
     if (has_halo) pull<D, S, R>(rs, slot_bytes, hlo, hf, hg);
     mo0 = node_moments<D, R>(f0, g0, k);
-    qm_cur = anomaly(mo0, D - 1);
+    qm_cur = anomaly(mo0, D - 1, k);
     core_publish(mo0, 0);
     halo_finish(hf, hg, 0);
   }
@@ -309,7 +321,7 @@ __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src,
       march_planes(more ? m + 2 : m + 1, rs);
       if (more) pull<D, S, R>(rs, slot_bytes, clo, fc, gc);
       mb = node_moments<D, R>(fb, gb, k);
-      qm_next = anomaly(mb, D - 1);
+      qm_next = anomaly(mb, D - 1, k);
       core_publish(mb, nb);
       halo_finish(hf, hg, nb);
       if (more && has_halo) pull<D, S, R>(rs, slot_bytes, hlo, hf, hg);
@@ -320,7 +332,7 @@ __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src,
       march_planes(m + 1, rs);
       pull<D, S, R>(rs, slot_bytes, clo, fb, gb);
       mb = node_moments<D, R>(fb, gb, k);
-      qm_next = anomaly(mb, D - 1);
+      qm_next = anomaly(mb, D - 1, k);
       core_publish(mb, nb);
       if (has_halo) pull<D, S, R>(rs, slot_bytes, hlo, hf, hg);
       halo_finish(hf, hg, nb);
@@ -393,9 +405,11 @@ __global__ void __launch_bounds__(256) init_kernel(const double* __restrict__ rh
   m.drho = (R)(r - p.rho0);
   m.T = (R)tt;
   m.dT = (R)(tt - p.T0);
-  m.u[0] = (R)u[n];
-  m.u[1] = (R)u[N + n];
-  m.u[2] = (D == 3) ? (R)u[2 * N + n] : (R)0;
+  for (int a = 0; a < 3; ++a) {
+    const double ua = a < D ? u[a * N + n] : 0.0;
+    m.u[a] = (R)ua;
+    m.du[a] = (R)(ua - p.u0[a]);
+  }
   m.omega = m.omega1 = (R)1;  // unused by the equilibria
   m.corr = (R)0;                // multiplies d = 0
   R d[3] = {0, 0, 0};
@@ -431,7 +445,7 @@ __global__ void __launch_bounds__(256) fields_kernel(const S* __restrict__ pops,
     if (cz) jz += cz > 0 ? v : -v;
   }
   const double rho = p.rho0 + s0;
-  const double ux = jx / rho, uy = jy / rho, uz = (D == 3) ? jz / rho : 0.0;
+  const double ux = (p.j0[0] + jx) / rho, uy = (p.j0[1] + jy) / rho, uz = (D == 3) ? (p.j0[2] + jz) / rho : 0.0;
   const double rhoE = p.rhoE0 + se;
   const double T = (rhoE / rho - 0.5 * (ux * ux + uy * uy + uz * uz)) * p.inv_Cv;
   fields[n] = rho;

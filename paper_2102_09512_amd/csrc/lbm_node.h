@@ -47,17 +47,37 @@ struct NodeMoments {
   R T;       // temperature
   R dT;      // T - T0
   R u[3];
+  R du[3];   // u - u0
   R pn[6];   // P - P^eq: xx, yy, zz, xy, xz, yz
   R irho;    // 1 / rho
   R omega, omega1;
   R corr;    // (2 - omega) / (2 rho omega), the factor of d_a in P^ex (Eq. (30))
 };
 
+// Constants of a step.  The reference state (rho0, u0, T0) of the FP32
+// deviation storage is zero for FP64 storage.  Per axis a, with
+// P0_a = T0 + u0_a^2, the reference factors of the product form are
+// psi0_a(c) = Psi_c(u0_a, P0_a) (also the a-factors of g^eq) and b0_a(c), the
+// b-factors of g^eq at (u0_a, T0); index c + 1.
 struct NodeConsts {
   double rho0, T0;
   double inv_Cv, Cv, Pr;
   double mu0, visc_exp, inv_Tref;
+  double u0[3], P0[3], psi0[3][3], b0[3][3];
+  float u0f[3], P0f[3], psi0f[3][3], b0f[3][3];
 };
+
+// The reference constants in compute precision.
+__device__ inline double ref(double d, float) { return d; }
+__device__ inline float ref(float, float f) { return f; }
+template <typename R>
+__device__ inline R ref_u0(const NodeConsts& k, int a) { return ref(R(k.u0[a]), k.u0f[a]); }
+template <typename R>
+__device__ inline R ref_P0(const NodeConsts& k, int a) { return ref(R(k.P0[a]), k.P0f[a]); }
+template <typename R>
+__device__ inline R ref_psi0(const NodeConsts& k, int a, int c) { return ref(R(k.psi0[a][c]), k.psi0f[a][c]); }
+template <typename R>
+__device__ inline R ref_b0(const NodeConsts& k, int a, int c) { return ref(R(k.b0[a][c]), k.b0f[a][c]); }
 
 // Reciprocal: the hardware approximation (about 1 ulp) in FP32, IEEE
 // division in FP64.
@@ -75,16 +95,49 @@ __device__ inline float viscosity(const NodeConsts& k, float T) {
 }
 
 // P - P^eq with P = sum c c f (Eq. (47)) and P^eq = rho T I + rho u u
-// (Eqs. (23), (25)); the isotropic part rho T - rho0 T0 = drho T0 + rho dT.
+// (Eqs. (23), (25)).  p holds the sums over the stored values, i.e. P minus
+// the reference rho0 (T0 I + u0 u0); so what is subtracted is
+// rho T - rho0 T0 = drho T0 + rho dT on the diagonal and
+// rho u_a u_b - rho0 u0_a u0_b = drho u_a u_b + rho0 (du_a u_b + u0_a du_b).
 template <int D, typename R>
 __device__ inline void nonequilibrium_pressure(NodeMoments<R>& m, const R* p, const NodeConsts& k) {
   const R iso = m.drho * (R)k.T0 + m.rho * m.dT;
-  m.pn[0] = p[0] - m.rho * m.u[0] * m.u[0] - iso;
-  m.pn[1] = p[1] - m.rho * m.u[1] * m.u[1] - iso;
-  m.pn[2] = (D == 3) ? p[2] - m.rho * m.u[2] * m.u[2] - iso : (R)0;
-  m.pn[3] = p[3] - m.rho * m.u[0] * m.u[1];
-  m.pn[4] = (D == 3) ? p[4] - m.rho * m.u[0] * m.u[2] : (R)0;
-  m.pn[5] = (D == 3) ? p[5] - m.rho * m.u[1] * m.u[2] : (R)0;
+  const R rho0 = (R)k.rho0;
+  auto uu = [&](int a, int b) {
+    return m.drho * m.u[a] * m.u[b] + rho0 * (m.du[a] * m.u[b] + ref_u0<R>(k, a) * m.du[b]);
+  };
+  m.pn[0] = p[0] - uu(0, 0) - iso;
+  m.pn[1] = p[1] - uu(1, 1) - iso;
+  m.pn[2] = (D == 3) ? p[2] - uu(2, 2) - iso : (R)0;
+  m.pn[3] = p[3] - uu(0, 1);
+  m.pn[4] = (D == 3) ? p[4] - uu(0, 2) : (R)0;
+  m.pn[5] = (D == 3) ? p[5] - uu(1, 2) : (R)0;
+}
+
+// u, u - u0 and T - T0 from the sums of the stored values (s0 = sum f,
+// j = sum c f, se = sum g), all in deviation form: u - u0 = (j - drho u0) / rho
+// and rho Cv (T - T0) = se - (1/2) sum_a [rho0 du_a (u_a + u0_a) + drho u_a^2]
+// - drho Cv T0, which follow from rho u = rho0 u0 + j and
+// rho E = rho0 (Cv T0 + |u0|^2 / 2) + se.
+template <int D, typename R>
+__device__ inline void velocity_temperature(NodeMoments<R>& m, R s0, const R* j, R se, const NodeConsts& k) {
+  m.drho = s0;
+  m.rho = (R)k.rho0 + s0;
+  m.irho = recip(m.rho);
+  R ke = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a < D) {
+      const R u0 = ref_u0<R>(k, a);
+      m.du[a] = (j[a] - s0 * u0) * m.irho;
+      m.u[a] = u0 + m.du[a];
+      ke += (R)k.rho0 * m.du[a] * (m.u[a] + u0) + s0 * m.u[a] * m.u[a];
+    } else {
+      m.du[a] = m.u[a] = (R)0;
+    }
+  }
+  m.dT = (se - (R)0.5 * ke - s0 * (R)(k.Cv * k.T0)) * m.irho * (R)k.inv_Cv;
+  m.T = (R)k.T0 + m.dT;
 }
 
 // omega from mu = (1/omega - 1/2) rho T (Eq. (92)): 1/omega = nu + 1/2 with
@@ -190,15 +243,7 @@ __device__ inline NodeMoments<R> node_moments(const R* f, const R* g, const Node
   moment_sums<D, R>(f, s0, j, p);
   const R se = total<D, R>(g);
   NodeMoments<R> m;
-  m.drho = s0;
-  m.rho = (R)k.rho0 + s0;
-  m.irho = recip(m.rho);
-  m.u[0] = j[0] * m.irho;
-  m.u[1] = j[1] * m.irho;
-  m.u[2] = (D == 3) ? j[2] * m.irho : (R)0;
-  const R ke = (R)0.5 * m.rho * (m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2]);
-  m.dT = (se - ke - m.drho * (R)(k.Cv * k.T0)) * m.irho * (R)k.inv_Cv;
-  m.T = (R)k.T0 + m.dT;
+  velocity_temperature<D, R>(m, s0, j, se, k);
   nonequilibrium_pressure<D, R>(m, p, k);
   relaxation_rates<R>(m, k);
   return m;
@@ -235,23 +280,22 @@ __device__ inline NodeMoments<float> node_moments_light(const float* f, const fl
   }
   const float se = total<D, float>(g);
   NodeMoments<float> m;
-  m.drho = s0;
-  m.rho = (float)k.rho0 + s0;
-  m.irho = recip(m.rho);
-  m.u[0] = jx * m.irho;
-  m.u[1] = jy * m.irho;
-  m.u[2] = jz * m.irho;
-  const float ke = 0.5f * m.rho * (m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2]);
-  m.dT = (se - ke - s0 * (float)(k.Cv * k.T0)) * m.irho * (float)k.inv_Cv;
-  m.T = (float)k.T0 + m.dT;
+  const float j[3] = {jx, jy, jz};
+  velocity_temperature<D, float>(m, s0, j, se, k);
   return m;
 }
 
-// Diagonal anomaly Qt_a = rho u_a (1 - 3T) - rho u_a^3, Eq. (29).
+// Diagonal anomaly Qt_a = rho u_a (1 - 3T - u_a^2), Eq. (29), less its value
+// at the reference state (a constant that no difference sees; zero for FP64
+// storage), formed from deviations: with w = 1 - 3T - u_a^2,
+// Qt_a - Qt0_a = (rho u_a - rho0 u0_a) w + rho0 u0_a (w - w0).
 template <typename R>
-__device__ inline R anomaly(const NodeMoments<R>& m, int a) {
-  const R u = m.u[a];
-  return m.rho * u * ((R)1 - (R)3 * m.T) - m.rho * u * u * u;
+__device__ inline R anomaly(const NodeMoments<R>& m, int a, const NodeConsts& k) {
+  const R u0 = ref_u0<R>(k, a), rho0 = (R)k.rho0;
+  const R w = (R)1 - (R)3 * m.T - m.u[a] * m.u[a];
+  const R dw = -(R)3 * m.dT - m.du[a] * (m.u[a] + u0);
+  const R dj = m.drho * m.u[a] + rho0 * m.du[a];
+  return dj * w + rho0 * u0 * dw;
 }
 
 // Upwind (Sec. III.A) or central (Sec. III.D.2) difference from the anomaly
@@ -262,80 +306,71 @@ __device__ inline R anomaly_derivative(int scheme, R u, R qm, R q0, R qp) {
   return (u > (R)0) ? (q0 - qm) : (qp - q0);
 }
 
-// Per-axis factors of f^ex - w:  Psi(c), and h(c) = drho Psi(c) + rho0 dPsi(c),
-// k(c) = rho0 Psi0(c), so that f^ex_i - w_i = h_x(cx) PY(cy,cz) + k_x(cx) DY(cy,cz)
-// with PY = Psi_y Psi_z and DY = Psi_y Psi_z - Psi0_y Psi0_z.
+// Per-axis factors of f^ex - w (w: the reference populations, zero for
+// FP64 storage): Psi(c) = Psi_c(u, P) and dPsi(c) = Psi(c) - psi0(c), so that
+// with h(c) = drho Psi(c) + rho0 dPsi(c) and kf(c) = rho0 psi0_x(c),
+// f^ex_i - w_i = h_x(cx) PY(cy,cz) + kf_x(cx) DY(cy,cz), PY = Psi_y Psi_z,
+// DY = Psi_y Psi_z - psi0_y psi0_z.
 template <typename R>
 struct AxisF {
   R psi[3], dpsi[3];
 };
 
+// u, du = u - u0, dP = P - P0 (P = T + u^2 + corr d, the diagonal of Eq. (30)).
 template <typename R, bool DEV>
-__device__ inline AxisF<R> axis_f(R u, R dP, R T0) {
-  // dP = P - T0, the departure of the diagonal second moment from the rest value
+__device__ inline AxisF<R> axis_f(R u, R du, R dP, R P0) {
   AxisF<R> a;
-  a.dpsi[1] = -dP;
-  a.dpsi[2] = (R)0.5 * (u + dP);
-  a.dpsi[0] = (R)0.5 * (-u + dP);
-  a.psi[1] = ((R)1 - T0) - dP;
-  a.psi[2] = (R)0.5 * (u + T0 + dP);
-  a.psi[0] = (R)0.5 * (-u + T0 + dP);
-  if (!DEV) {
+  a.psi[1] = ((R)1 - P0) - dP;
+  a.psi[2] = (R)0.5 * (u + P0 + dP);
+  a.psi[0] = (R)0.5 * (-u + P0 + dP);
+  if (DEV) {
+    a.dpsi[1] = -dP;
+    a.dpsi[2] = (R)0.5 * (du + dP);
+    a.dpsi[0] = (R)0.5 * (-du + dP);
+  } else {
     a.dpsi[0] = a.dpsi[1] = a.dpsi[2] = (R)0;
   }
   return a;
 }
 
-// Per-axis factors of g^eq - w (see the header comment).
+// Per-axis factors of g^eq (Eq. (42) in closed form): a(c) = Psi_c(u, T + u^2),
+// b(0) = u^2/2 - B2, b(+-1) = (+-B1 + B2)/2 with B1 = u (u^2 + 2T)/2,
+// B2 = (u^4 + 5 u^2 T + 2 T^2)/2, and their departures da, db from the
+// reference (u0, T0), formed from du and dT so that no large terms cancel.
 template <typename R>
 struct AxisG {
   R a[3], b[3], da[3], db[3];
 };
 
 template <typename R, bool DEV>
-__device__ inline AxisG<R> axis_g(R u, R T, R dT, R T0) {
+__device__ inline AxisG<R> axis_g(R u, R du, R u0, R T, R dT, R T0) {
   AxisG<R> x;
   const R u2 = u * u;
   const R B1 = (R)0.5 * u * (u2 + (R)2 * T);
-  const R B2v = (R)0.5 * (u2 * u2 + (R)5 * u2 * T);  // B2 without the T^2 term
+  const R B2 = (R)0.5 * (u2 * u2 + (R)5 * u2 * T) + T * T;
   x.a[1] = (R)1 - T - u2;
   x.a[2] = (R)0.5 * (u + T + u2);
   x.a[0] = (R)0.5 * (-u + T + u2);
-  const R B2 = B2v + T * T;
   x.b[1] = (R)0.5 * u2 - B2;
   x.b[2] = (R)0.5 * (B1 + B2);
   x.b[0] = (R)0.5 * (-B1 + B2);
   if (DEV) {
-    const R dT2 = dT * (T + T0);  // T^2 - T0^2
-    x.da[1] = -(dT + u2);
-    x.da[2] = (R)0.5 * (u + dT + u2);
-    x.da[0] = (R)0.5 * (-u + dT + u2);
-    x.db[1] = (R)0.5 * u2 - B2v - dT2;
-    x.db[2] = (R)0.5 * (B1 + B2v + dT2);
-    x.db[0] = (R)0.5 * (-B1 + B2v + dT2);
+    const R su = u + u0;
+    const R du2 = du * su;                                    // u^2 - u0^2
+    const R u02 = u0 * u0;
+    const R dB1 = (R)0.5 * du * (u2 + u * u0 + u02) + du * T + u0 * dT;
+    const R dB2 = (R)0.5 * du2 * (u2 + u02) + (R)2.5 * (du2 * T + u02 * dT) + dT * (T + T0);
+    x.da[1] = -(dT + du2);
+    x.da[2] = (R)0.5 * (du + dT + du2);
+    x.da[0] = (R)0.5 * (-du + dT + du2);
+    x.db[1] = (R)0.5 * du2 - dB2;
+    x.db[2] = (R)0.5 * (dB1 + dB2);
+    x.db[0] = (R)0.5 * (-dB1 + dB2);
   } else {
     x.da[0] = x.da[1] = x.da[2] = (R)0;
     x.db[0] = x.db[1] = x.db[2] = (R)0;
   }
   return x;
-}
-
-// Rest-state per-axis factors at temperature T0 (u = 0).
-template <typename R>
-struct Rest {
-  R psi0[3], a0[3], b0[3];
-};
-
-template <typename R>
-__device__ inline Rest<R> rest_factors(R T0) {
-  Rest<R> r;
-  r.psi0[1] = (R)1 - T0;
-  r.psi0[0] = r.psi0[2] = (R)0.5 * T0;
-  r.a0[1] = (R)1 - T0;
-  r.a0[0] = r.a0[2] = (R)0.5 * T0;
-  r.b0[1] = -T0 * T0;
-  r.b0[0] = r.b0[2] = (R)0.5 * T0 * T0;
-  return r;
 }
 
 // Writes (f^ex - w) and (g^eq - w) for all Q populations (the equilibria with
@@ -344,16 +379,16 @@ __device__ inline Rest<R> rest_factors(R T0) {
 template <int D, typename R, bool DEV>
 __device__ inline void equilibria(const NodeMoments<R>& m, const R* d, const NodeConsts& k, R* fe, R* ge) {
   const R T0 = (R)k.T0, rho0 = (R)k.rho0;
-  const Rest<R> rs = rest_factors<R>(T0);
   const R corr = m.corr;
 
   AxisF<R> F[3];
   AxisG<R> G[3];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    const R dP = m.dT + m.u[a] * m.u[a] + corr * d[a];
-    F[a] = axis_f<R, DEV>(m.u[a], dP, T0);
-    G[a] = axis_g<R, DEV>(m.u[a], m.T, m.dT, T0);
+    const R u0 = ref_u0<R>(k, a);
+    const R dP = m.dT + m.du[a] * (m.u[a] + u0) + corr * d[a];  // P - P0
+    F[a] = axis_f<R, DEV>(m.u[a], m.du[a], dP, ref_P0<R>(k, a));
+    G[a] = axis_g<R, DEV>(m.u[a], m.du[a], u0, m.T, m.dT, T0);
   }
   const R eps = (R)k.Cv * m.T;
   const R deps = (R)k.Cv * m.dT;
@@ -364,11 +399,11 @@ __device__ inline void equilibria(const NodeMoments<R>& m, const R* d, const Nod
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     hx[c] = m.drho * F[0].psi[c] + (DEV ? rho0 * F[0].dpsi[c] : (R)0);
-    kx[c] = DEV ? rho0 * rs.psi0[c] : (R)0;
+    kx[c] = DEV ? rho0 * ref_psi0<R>(k, 0, c) : (R)0;
     G1[c] = m.drho * G[0].a[c] + (DEV ? rho0 * G[0].da[c] : (R)0);
     G2[c] = m.drho * G[0].b[c] + (DEV ? rho0 * G[0].db[c] : (R)0);
-    G3[c] = DEV ? rho0 * rs.a0[c] : (R)0;
-    G4[c] = DEV ? rho0 * rs.b0[c] : (R)0;
+    G3[c] = DEV ? rho0 * ref_psi0<R>(k, 0, c) : (R)0;
+    G4[c] = DEV ? rho0 * ref_b0<R>(k, 0, c) : (R)0;
   }
 
   constexpr int NP = (D == 3) ? 9 : 3;  // (cy, cz) pairs
@@ -378,12 +413,12 @@ __device__ inline void equilibria(const NodeMoments<R>& m, const R* d, const Nod
     R PY, DY, A, Bs, dA, dBs;
     if (D == 3) {
       PY = F[1].psi[jy] * F[2].psi[jz];
-      DY = F[1].dpsi[jy] * F[2].psi[jz] + rs.psi0[jy] * F[2].dpsi[jz];
+      const R p0y = ref_psi0<R>(k, 1, jy), b0y = ref_b0<R>(k, 1, jy);  // a0 = psi0
+      DY = F[1].dpsi[jy] * F[2].psi[jz] + p0y * F[2].dpsi[jz];
       A = G[1].a[jy] * G[2].a[jz];
       Bs = G[1].b[jy] * G[2].a[jz] + G[1].a[jy] * G[2].b[jz];
-      dA = G[1].da[jy] * G[2].a[jz] + rs.a0[jy] * G[2].da[jz];
-      dBs = G[1].db[jy] * G[2].a[jz] + rs.b0[jy] * G[2].da[jz] + G[1].da[jy] * G[2].b[jz] +
-            rs.a0[jy] * G[2].db[jz];
+      dA = G[1].da[jy] * G[2].a[jz] + p0y * G[2].da[jz];
+      dBs = G[1].db[jy] * G[2].a[jz] + b0y * G[2].da[jz] + G[1].da[jy] * G[2].b[jz] + p0y * G[2].db[jz];
     } else {
       PY = F[1].psi[jy];
       DY = F[1].dpsi[jy];

@@ -37,6 +37,7 @@ def test_default_options(lbm):
     assert list(o.bc) == [0, 0, 0]
     assert o.visc_exponent == 0.0 and o.rho_ref == 1.0 and abs(o.T_ref - 1 / 3) < 1e-15
     assert o.deriv_scheme == lbm.LBM_DERIV_UPWIND and list(o.tile) == [0, 0, 0]
+    assert list(o.u_ref) == [0.0, 0.0, 0.0]
 
 
 @pytest.mark.parametrize("args,needle", [
@@ -62,6 +63,8 @@ def test_create_rejects_bad_arguments(lbm, args, needle):
     (dict(T_ref=0.0), "T_ref"),
     (dict(rho_ref=-1.0), "rho_ref"),
     (dict(tile=(48, 4, 8)), "tile"),
+    (dict(u_ref=(1.5, 0.0, 0.0)), "u_ref"),
+    (dict(u_ref=(0.0, float("nan"), 0.0)), "u_ref"),
 ])
 def test_create_rejects_bad_options(lbm, kw, needle):
     with pytest.raises(lbm.LbmError) as e:

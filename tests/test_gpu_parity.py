@@ -26,13 +26,13 @@ def rel(a, b):
 
 
 def run_gpu(D, dims, fields, steps, mu, Pr=0.71, gamma=1.4, fp32=False, bc=(0, 0, 0), visc_exp=0.0, T_ref=0.15,
-            deriv=0, device_io=True, tile=None, want_state=True, want_diag=False):
+            deriv=0, device_io=True, tile=None, want_state=True, want_diag=False, u_ref=None):
     lbm = _lbm()
     print(f"[gpu case] D={D} dims={dims} steps={steps} fp32={fp32} bc={bc} deriv={deriv} tile={tile} "
           f"io={'device' if device_io else 'host'}", flush=True)
     rho, u, T = fields
     h = lbm.lbm_create(D, dims, gamma, Pr, mu, precision=lbm.LBM_FP32_DEV if fp32 else lbm.LBM_FP64, bc=bc,
-                       visc_exponent=visc_exp, T_ref=T_ref, rho_ref=1.0, deriv_scheme=deriv, tile=tile)
+                       visc_exponent=visc_exp, T_ref=T_ref, rho_ref=1.0, deriv_scheme=deriv, tile=tile, u_ref=u_ref)
     try:
         lbm.lbm_set_stream(h, torch.cuda.current_stream())
         if device_io:
@@ -173,16 +173,18 @@ def test_fp32_deviation_turbulence_3d_central():
     check_fields(out, s, 1e-5)
 
 
-def test_fp32_deviation_upwind_without_sign_changes():
+@pytest.mark.parametrize("u_ref", [None, (0.1, 0.1, 0.1)])
+def test_fp32_deviation_upwind_without_sign_changes(u_ref):
     """FP32 deviation storage vs the FP64 oracle with the upwind anomaly
     difference, on a flow whose velocity components stay away from zero
     (mean flow 0.1 + perturbations of at most 0.05), so both runs take the
-    same upwind branches (see test_fp32_upwind_sign_ambiguity)."""
+    same upwind branches (see test_fp32_upwind_sign_ambiguity); deviations
+    from the rest state and from the mean-flow state."""
     dims = (40, 36, 32)
     rho, u, T = I.smooth_random(3, dims, seed=6, rho_amp=0.05, u_amp=0.05, T_amp=0.02)
     u = u + 0.1
     kw = dict(mu=0.01, Pr=0.7, visc_exp=0.76, T_ref=0.15)
-    out, _, _ = run_gpu(3, dims, (rho, u, T), 100, fp32=True, want_state=False, **kw)
+    out, _, _ = run_gpu(3, dims, (rho, u, T), 100, fp32=True, want_state=False, u_ref=u_ref, **kw)
     s = run_oracle(3, dims, (rho, u, T), 100, **kw)
     assert np.abs(s.moments()[1]).min() > 1e-3
     check_fields(out, s, 1e-5)
@@ -208,10 +210,12 @@ def test_fp32_upwind_sign_ambiguity():
     assert abs(d["kinetic_energy"] - r["kinetic"]) <= 1e-5 * r["kinetic"]
 
 
-def test_fp32_deviation_shock_vortex_crop():
+@pytest.mark.parametrize("u_ref", [None, "upstream"])
+def test_fp32_deviation_shock_vortex_crop(u_ref):
     rho, u, T, rh = I.shock_vortex(256, 128, r_v=16.0, x_s=128)
     kw = dict(mu=0.0198, Pr=0.75, bc=(1, 0, 0), T_ref=0.05)
-    out, _, _ = run_gpu(2, (256, 128), (rho, u, T), 100, fp32=True, want_state=False, **kw)
+    ur = (float(u[0, 0, 0, 0]), 0.0) if u_ref else None  # the free stream ahead of the shock
+    out, _, _ = run_gpu(2, (256, 128), (rho, u, T), 100, fp32=True, want_state=False, u_ref=ur, **kw)
     s = run_oracle(2, (256, 128), (rho, u, T), 100, **kw)
     check_fields(out, s, 1e-5)
 
@@ -433,6 +437,7 @@ def test_fp32_d2q9_tiles(tile):
     """Each D2Q9 launch width on the FP32 shock-vortex case, within 1e-5 of the oracle."""
     rho, u, T, rh = I.shock_vortex(300, 70, r_v=12.0, x_s=150)
     kw = dict(mu=0.0198, Pr=0.75, bc=(1, 0, 0), T_ref=0.05)
-    out, _, _ = run_gpu(2, (300, 70), (rho, u, T), 80, fp32=True, want_state=False, tile=tile, **kw)
+    ur = (float(u[0, 0, 0, 0]), 0.0)  # deviations from the free stream
+    out, _, _ = run_gpu(2, (300, 70), (rho, u, T), 80, fp32=True, want_state=False, tile=tile, u_ref=ur, **kw)
     s = run_oracle(2, (300, 70), (rho, u, T), 80, **kw)
     check_fields(out, s, 1e-5)
