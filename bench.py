@@ -1,23 +1,28 @@
 #!/usr/bin/env python3
 """Throughput of the fused stream-and-collide on one MI355X.
 
-Workload (default): 3-D compressible decaying turbulence, D3Q27, 256^3
-periodic nodes, FP32 deviation storage; seeded solenoidal velocity with
-E(k) ~ k^4 exp(-2 (k/k0)^2), k0 = 4 (2 pi/256), Ma_t = 0.5, Re_lambda = 72,
-rho = 1, T0 = 0.15, mu = mu0 (T/T0)^0.76, Pr = 0.7, gamma = 1.4.
+Workload (default, --workload turbulence3d): 3-D compressible decaying
+turbulence, D3Q27, 256^3 periodic nodes, FP32 deviation storage; seeded
+solenoidal velocity with E(k) ~ k^4 exp(-2 (k/k0)^2), k0 = 4 (2 pi/256),
+Ma_t = 0.5, Re_lambda = 72, rho = 1, T0 = 0.15, mu = mu0 (T/T0)^0.76,
+Pr = 0.7, gamma = 1.4.
+
+--workload shockvortex2d: the 2-D shock-vortex interaction, D2Q9 1024^2 (a
+standing Ma 1.2 shock at x = 512 with an isentropic vortex upstream); its
+FP32 working set (151 MB) fits in the 256 MB last-level cache, so its HBM
+fraction is not a roofline figure.
 
 One timed step = one lbm_step (one launch of the fused kernel) over the whole
 box; the diagnostics reduction runs every --diag-every steps inside the timed
 region.  Prints one JSON line (metric MLUPS) with the roofline of the step
-kernel (algorithmic bytes per node update 2 x Q x (read + write) x 4 B = 432 B)
-and the CPU oracle timed on a bounded sample of the same workload.
+kernel (algorithmic bytes per node update 2 x Q x (read + write) x word) and
+the CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -55,15 +60,34 @@ def measured_traffic(workload: str, precision: str):
     return None
 
 
-def cpu_baseline(fields, dims, mu, budget_s: float):
+def make_workload(name: str, n: int):
+    """Inputs and physical parameters of a workload (seeded, synthetic)."""
+    from paper_2102_09512_amd import inputs
+
+    if name == "turbulence3d":
+        fields = inputs.turbulence(3, n, seed=0, k0_index=4, Ma_t=0.5, T0=0.15)
+        mu = inputs.turbulence_viscosity(n, k0_index=4, Ma_t=0.5, T0=0.15, Re_lambda=72.0)
+        return dict(D=3, dims=(n, n, n), fields=fields, gamma=1.4, Pr=0.7, mu=mu, visc_exp=0.76, T_ref=0.15,
+                    rho_ref=1.0, u_ref=None, bc=(0, 0, 0),
+                    label=f"decaying-turbulence D3Q27 {n}^3 periodic {{prec}}-storage Ma_t=0.5 Re_lambda=72")
+    rho, u, T, _ = inputs.shock_vortex(n, n, r_v=32.0 * n / 1024, x_s=n // 2)
+    return dict(D=2, dims=(n, n, 1), fields=(rho, u, T), gamma=1.4, Pr=0.75, mu=0.0198, visc_exp=0.0, T_ref=0.05,
+                rho_ref=1.0, u_ref=(float(u[0, 0, 0, 0]), 0.0), bc=(1, 0, 0),
+                label=f"shock-vortex D2Q9 {n}^2 x-zero-gradient {{prec}}-storage Ma_s=1.2 Ma_v=0.25")
+
+
+def cpu_baseline(w, budget_s: float):
     """The oracle as it stands, on the GPU host's cores, over whole steps of
-    the same 256^3 input until about budget_s seconds of stepping."""
+    the same input until about budget_s seconds of stepping."""
     import oracle
 
     threads = oracle.num_threads()
-    _log(f"[cpu baseline] oracle with {threads} threads on {dims}")
-    s = oracle.Sim(3, dims, gamma=1.4, Pr=0.7, mu=mu, visc_exp=0.76, T_ref=0.15)
-    s.init(*fields)
+    D, dims = w["D"], w["dims"]
+    odims = dims if D == 3 else dims[:2]
+    _log(f"[cpu baseline] oracle with {threads} threads on {odims}")
+    s = oracle.Sim(D, odims, gamma=w["gamma"], Pr=w["Pr"], mu=w["mu"], visc_exp=w["visc_exp"], T_ref=w["T_ref"],
+                   bc=w["bc"])
+    s.init(*w["fields"])
     N = dims[0] * dims[1] * dims[2]
     steps, t_total = 0, 0.0
     while t_total < budget_s and steps < 50:
@@ -73,8 +97,9 @@ def cpu_baseline(fields, dims, mu, budget_s: float):
         steps += 1
         _log(f"[cpu baseline] step {steps}: {t_total:.1f} s")
     del s
+    shape = "x".join(str(d) for d in odims)
     return {"value": N * steps / t_total / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} full step(s) of the same {dims[0]}x{dims[1]}x{dims[2]} D3Q27 input, FP64, "
+            "sample": f"{steps} full step(s) of the same {shape} D{D}Q{3 ** D} input, FP64, "
                       f"{t_total:.1f} s of stepping (initialisation excluded)"}
 
 
@@ -83,7 +108,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--n", type=int, default=256, help="box edge (default: the 256^3 workload)")
+    ap.add_argument("--workload", choices=["turbulence3d", "shockvortex2d"], default="turbulence3d")
+    ap.add_argument("--n", type=int, default=0, help="box edge (default 256 for turbulence3d, 1024 for shockvortex2d)")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--tile", type=str, default="", help="bx,by,chunk of the step kernel")
     ap.add_argument("--diag-every", type=int, default=100)
@@ -97,30 +123,29 @@ def main():
               "decomposition is described in DESIGN.md but not built.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    from paper_2102_09512_amd import inputs, lbm
+    from paper_2102_09512_amd import lbm
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    n = args.n
-    dims = (n, n, n)
-    N = n ** 3
-    Q = 27
+    n = args.n or (256 if args.workload == "turbulence3d" else 1024)
+    _log(f"[bench] generating the {args.workload} input, n = {n}")
+    w = make_workload(args.workload, n)
+    D, dims = w["D"], w["dims"]
+    N = dims[0] * dims[1] * dims[2]
+    Q = 3 ** D
     word = 4 if args.precision == "fp32" else 8
     bytes_per_node = 2 * Q * 2 * word
 
-    _log(f"[bench] generating the {n}^3 turbulence input")
-    fields = inputs.turbulence(3, n, seed=0, k0_index=4, Ma_t=0.5, T0=0.15)
-    mu = inputs.turbulence_viscosity(n, k0_index=4, Ma_t=0.5, T0=0.15, Re_lambda=72.0)
-
     stream = torch.cuda.current_stream(dev)
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
-    h = lbm.lbm_create(3, dims, 1.4, 0.7, mu, precision=lbm.LBM_FP32_DEV if word == 4 else lbm.LBM_FP64,
-                       visc_exponent=0.76, T_ref=0.15, rho_ref=1.0, tile=tile)
+    h = lbm.lbm_create(D, dims, w["gamma"], w["Pr"], w["mu"],
+                       precision=lbm.LBM_FP32_DEV if word == 4 else lbm.LBM_FP64, bc=w["bc"],
+                       visc_exponent=w["visc_exp"], T_ref=w["T_ref"], rho_ref=w["rho_ref"], u_ref=w["u_ref"],
+                       tile=tile)
     lbm.lbm_set_stream(h, stream)
-    lbm.lbm_init_fields(h, *(torch.from_numpy(a).to(dev) for a in fields))
+    lbm.lbm_init_fields(h, *(torch.from_numpy(a).to(dev) for a in w["fields"]))
 
     _log(f"[bench] warmup {args.warmup} steps")
     lbm.lbm_step(h, args.warmup)
@@ -130,7 +155,6 @@ def main():
     # stream the library launches on bracket every step launch
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    diags = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -138,7 +162,7 @@ def main():
         lbm.lbm_step(h, 1)
         ends[k].record(stream)
         if args.diag_every and (k + 1) % args.diag_every == 0:
-            diags.append(lbm.lbm_diagnostics(h))
+            lbm.lbm_diagnostics(h)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kernel_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
@@ -171,10 +195,11 @@ def main():
 
     mlups = N * args.steps / wall / 1e6
     achieved = bytes_per_node * N / avg_kernel_s / 1e9
-    workload = f"decaying-turbulence D3Q27 {n}^3 periodic {args.precision}-storage Ma_t=0.5 Re_lambda=72"
+    workload = w["label"].format(prec=args.precision)
     traffic = measured_traffic(workload, args.precision)
+    lattice = f"D{D}Q{Q}"
     out = {
-        "metric": "MLUPS (D3Q27 fused stream+collide)",
+        "metric": f"MLUPS ({lattice} fused stream+collide)",
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -185,8 +210,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if word == 4 else "f64",
-        "data": "synthetic (seeded solenoidal turbulence, no dataset)",
-        "config": {"workload": workload, "lattice": "D3Q27", "nodes": N, "dims": list(dims),
+        "data": "synthetic (seeded, no dataset)",
+        "config": {"workload": workload, "lattice": lattice, "nodes": N, "dims": list(dims[:D]),
                    "bytes_per_node_update": bytes_per_node, "diag_every": args.diag_every,
                    "tile": list(tile) if tile else "default", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -198,8 +223,10 @@ def main():
         "kernel_source": kernel_source_hash(),
         "final_step_nonfinite": d["nonfinite"],
     }
+    if D == 2:
+        out["roofline"]["note"] = "working set fits in the last-level cache; not an HBM roofline figure"
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(fields, dims, mu, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
         out["cpu_baseline"]["gpu_speedup"] = round(mlups / out["cpu_baseline"]["value"], 1)
     print(json.dumps(out), flush=True)
 

@@ -162,6 +162,44 @@ __device__ inline void pull(const __amdgpu_buffer_rsrc_t* rs, unsigned slot_byte
   }
 }
 
+// Density, velocity and temperature of a node from its pulled populations,
+// loaded and summed in batches of nine velocities so that few registers hold
+// loaded values at a time (used for the halo node where registers are short).
+template <int D, typename S, typename R>
+__device__ inline NodeMoments<R> pulled_moments_batched(const __amdgpu_buffer_rsrc_t* rs, unsigned slot_bytes,
+                                                        const unsigned* lo, const NodeConsts& k) {
+  constexpr int Q = lat_q(D);
+  double s0 = 0, j[3] = {0, 0, 0}, se = 0;
+#pragma unroll
+  for (int b = 0; b < Q; b += 9) {
+    R f[9], g[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const int i = b + q;
+      const int cx = vx(i);
+      const int cy = (D == 3) ? vy(i) : 0;
+      const int cm = (D == 3) ? vz(i) : vy(i);
+      const auto v = Buf<S>::load(rs[1 - cm], lo[(1 - cy) * 3 + (1 - cx)], (unsigned)i * slot_bytes);
+      f[q] = (R)v.x;
+      g[q] = (R)v.y;
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const int i = b + q;
+      const int cx = vx(i), cy = vy(i), cz = (D == 3) ? vz(i) : 0;
+      s0 += f[q];
+      se += g[q];
+      if (cx) j[0] += cx > 0 ? f[q] : -f[q];
+      if (cy) j[1] += cy > 0 ? f[q] : -f[q];
+      if (cz) j[2] += cz > 0 ? f[q] : -f[q];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  NodeMoments<R> m;
+  velocity_temperature<D, R>(m, s0, j, se, k);
+  return m;
+}
+
 template <int D, bool DEV, typename S, int BX, int BY>
 __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src, S* __restrict__ dst,
                                                       const StepParams p) {
@@ -256,12 +294,8 @@ __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src,
 #pragma unroll
     for (int j = 0; j < 3; ++j) rs[j] = plane_rsrc(src + (long long)fix_near(mn + j - 1, nm, bcm) * sm, plane_bytes);
   };
-  // The halo node's anomaly, from its populations, into LDS buffer buf.
-  auto halo_finish = [&](const R* f, const R* g, int buf) {
-    if (!has_halo) return;
-    NodeMoments<R> mm;
-    if constexpr (DEV) mm = node_moments_light<D>(f, g, k);
-    else mm = node_moments<D, R>(f, g, k);
+  // The halo node's anomaly into LDS buffer buf.
+  auto halo_store = [&](const NodeMoments<R>& mm, int buf) {
     if (D == 3) {
       if (hslot == 0) lq1[buf][0][t] = anomaly(mm, 1, k);
       else if (hslot == 1) lq1[buf][BY + 1][t - BX] = anomaly(mm, 1, k);
@@ -270,6 +304,16 @@ __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src,
     } else {
       lq0[buf][0][hslot == 2 ? 0 : BX + 1] = anomaly(mm, 0, k);
     }
+  };
+  // ... from populations already in registers (FP32 only) ...
+  auto halo_finish = [&](const R* f, const R* g, int buf) {
+    if constexpr (DEV) {
+      if (has_halo) halo_store(node_moments_light<D>(f, g, k), buf);
+    }
+  };
+  // ... or loaded now, in batches.
+  auto halo_direct = [&](const __amdgpu_buffer_rsrc_t* rs, int buf) {
+    if (has_halo) halo_store(pulled_moments_batched<D, S, R>(rs, slot_bytes, hlo, k), buf);
   };
   // Own node's in-plane anomalies into LDS buffer buf.
   auto core_publish = [&](const NodeMoments<R>& mm, int buf) {
@@ -296,11 +340,10 @@ __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src,
     __amdgpu_buffer_rsrc_t rs[3];
     march_planes(m0, rs);
     pull<D, S, R>(rs, slot_bytes, clo, f0, g0);
-    if (has_halo) pull<D, S, R>(rs, slot_bytes, hlo, hf, hg);
     mo0 = node_moments<D, R>(f0, g0, k);
     qm_cur = anomaly(mo0, D - 1, k);
     core_publish(mo0, 0);
-    halo_finish(hf, hg, 0);
+    halo_direct(rs, 0);
   }
   if (PF2) {
     __amdgpu_buffer_rsrc_t rs[3];
@@ -334,8 +377,7 @@ __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src,
       mb = node_moments<D, R>(fb, gb, k);
       qm_next = anomaly(mb, D - 1, k);
       core_publish(mb, nb);
-      if (has_halo) pull<D, S, R>(rs, slot_bytes, hlo, hf, hg);
-      halo_finish(hf, hg, nb);
+      halo_direct(rs, nb);
     }
     // collide plane m
     R dd[3];
@@ -619,7 +661,12 @@ Tile default_tile(int D, int precision, const int64_t n[3]) {
     chunk = chunk < 16 ? 16 : (chunk > 256 ? 256 : chunk);
     return Tile{64, 4, (int)(chunk < n[2] ? chunk : n[2])};
   }
-  return Tile{128, 1, (int)(n[1] < 32 ? n[1] : 32)};
+  // D2Q9: rows of 128; chunks short enough for about 1024 work-groups (the
+  // whole 2-D field is small), between 4 and 32 rows.
+  const int64_t tiles = (n[0] + 127) / 128;
+  int64_t chunk = n[1] * tiles / 1024;
+  chunk = chunk < 4 ? 4 : (chunk > 32 ? 32 : chunk);
+  return Tile{128, 1, (int)(chunk < n[1] ? chunk : n[1])};
 }
 
 bool tile_supported(int D, int precision, const Tile& t) {

@@ -119,25 +119,66 @@ __device__ inline void nonequilibrium_pressure(NodeMoments<R>& m, const R* p, co
 // and rho Cv (T - T0) = se - (1/2) sum_a [rho0 du_a (u_a + u0_a) + drho u_a^2]
 // - drho Cv T0, which follow from rho u = rho0 u0 + j and
 // rho E = rho0 (Cv T0 + |u0|^2 / 2) + se.
+// The sums and this recovery are done in FP64 for every storage precision.
 template <int D, typename R>
-__device__ inline void velocity_temperature(NodeMoments<R>& m, R s0, const R* j, R se, const NodeConsts& k) {
-  m.drho = s0;
-  m.rho = (R)k.rho0 + s0;
-  m.irho = recip(m.rho);
-  R ke = 0;
+__device__ inline void velocity_temperature(NodeMoments<R>& m, double s0, const double* j, double se,
+                                            const NodeConsts& k) {
+  const double rho = k.rho0 + s0, irho = 1.0 / rho;
+  double ke = 0.0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (a < D) {
-      const R u0 = ref_u0<R>(k, a);
-      m.du[a] = (j[a] - s0 * u0) * m.irho;
-      m.u[a] = u0 + m.du[a];
-      ke += (R)k.rho0 * m.du[a] * (m.u[a] + u0) + s0 * m.u[a] * m.u[a];
+      const double u0 = k.u0[a];
+      const double du = (j[a] - s0 * u0) * irho;
+      const double u = u0 + du;
+      ke += k.rho0 * du * (u + u0) + s0 * u * u;
+      m.du[a] = (R)du;
+      m.u[a] = (R)u;
     } else {
       m.du[a] = m.u[a] = (R)0;
     }
   }
-  m.dT = (se - (R)0.5 * ke - s0 * (R)(k.Cv * k.T0)) * m.irho * (R)k.inv_Cv;
-  m.T = (R)k.T0 + m.dT;
+  const double dT = (se - 0.5 * ke - s0 * (k.Cv * k.T0)) * irho * k.inv_Cv;
+  m.drho = (R)s0;
+  m.rho = (R)rho;
+  m.irho = (R)irho;
+  m.dT = (R)dT;
+  m.T = (R)(k.T0 + dT);
+}
+
+// FP64 sums of the conserved moments of the stored values: s0 = sum f,
+// j = sum c f, se = sum g, row by row as in moment_sums.
+template <int D, typename R>
+__device__ inline void conserved_sums(const R* f, const R* g, double& s0, double* j, double& se) {
+  constexpr int NR = (D == 3) ? 9 : 3;
+  double r0[NR], rx[NR], rg[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const double a = (double)f[3 * r], b = (double)f[3 * r + 1], c = (double)f[3 * r + 2];
+    rx[r] = c - a;
+    r0[r] = (c + a) + b;
+    rg[r] = ((double)g[3 * r + 2] + (double)g[3 * r]) + (double)g[3 * r + 1];
+  }
+  if (D == 3) {
+    double l0[3], lx[3], lg[3];
+#pragma unroll
+    for (int z = 0; z < 3; ++z) {
+      l0[z] = (r0[3 * z] + r0[3 * z + 2]) + r0[3 * z + 1];
+      lx[z] = (rx[3 * z] + rx[3 * z + 2]) + rx[3 * z + 1];
+      lg[z] = (rg[3 * z] + rg[3 * z + 2]) + rg[3 * z + 1];
+    }
+    s0 = (l0[0] + l0[2]) + l0[1];
+    se = (lg[0] + lg[2]) + lg[1];
+    j[0] = (lx[0] + lx[2]) + lx[1];
+    j[1] = ((r0[2] - r0[0]) + (r0[8] - r0[6])) + (r0[5] - r0[3]);
+    j[2] = l0[2] - l0[0];
+  } else {
+    s0 = (r0[0] + r0[2]) + r0[1];
+    se = (rg[0] + rg[2]) + rg[1];
+    j[0] = (rx[0] + rx[2]) + rx[1];
+    j[1] = r0[2] - r0[0];
+    j[2] = 0.0;
+  }
 }
 
 // omega from mu = (1/omega - 1/2) rho T (Eq. (92)): 1/omega = nu + 1/2 with
@@ -232,16 +273,17 @@ __device__ inline R total(const R* g) {
   return (r[0] + r[2]) + r[1];
 }
 
-// Moments of the post-streaming populations f, g (Eqs. (3)-(7)); deviations
-// from the rest state (rho0, 0, T0) when the storage is FP32.  FP64 storage
-// (rho0 = 0, rhoE0 = 0) sums the full populations.  The FP32 path keeps
-// every quantity a deviation: rho Cv (T - T0) = sum g - rho |u|^2 / 2 -
-// (rho - rho0) Cv T0, so no large terms cancel.
+// Moments of the post-streaming populations f, g (Eqs. (3)-(7), (47)): the
+// stored values are deviations from the reference state (rho0, u0, T0) for
+// FP32 storage and full populations for FP64 storage (reference zero).
+// rho, u and T come from FP64 sums in deviation form (velocity_temperature);
+// P - P^eq is summed in the compute precision.
 template <int D, typename R>
 __device__ inline NodeMoments<R> node_moments(const R* f, const R* g, const NodeConsts& k) {
-  R s0, j[3], p[6];
-  moment_sums<D, R>(f, s0, j, p);
-  const R se = total<D, R>(g);
+  R s0r, jr[3], p[6];
+  moment_sums<D, R>(f, s0r, jr, p);  // only p is used: the conserved sums are FP64
+  double s0, j[3], se;
+  conserved_sums<D, R>(f, g, s0, j, se);
   NodeMoments<R> m;
   velocity_temperature<D, R>(m, s0, j, se, k);
   nonequilibrium_pressure<D, R>(m, p, k);
@@ -254,33 +296,9 @@ __device__ inline NodeMoments<R> node_moments(const R* f, const R* g, const Node
 // march chunk) in the FP32 kernels.
 template <int D>
 __device__ inline NodeMoments<float> node_moments_light(const float* f, const float* g, const NodeConsts& k) {
-  constexpr int NR = (D == 3) ? 9 : 3;
-  float r0[NR], rx[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    rx[r] = f[3 * r + 2] - f[3 * r];
-    r0[r] = (f[3 * r + 2] + f[3 * r]) + f[3 * r + 1];
-  }
-  float s0, jx, jy, jz = 0.f;
-  if (D == 3) {
-    float l0[3], lx[3];
-#pragma unroll
-    for (int z = 0; z < 3; ++z) {
-      l0[z] = (r0[3 * z] + r0[3 * z + 2]) + r0[3 * z + 1];
-      lx[z] = (rx[3 * z] + rx[3 * z + 2]) + rx[3 * z + 1];
-    }
-    s0 = (l0[0] + l0[2]) + l0[1];
-    jx = (lx[0] + lx[2]) + lx[1];
-    jy = ((r0[2] - r0[0]) + (r0[8] - r0[6])) + (r0[5] - r0[3]);
-    jz = l0[2] - l0[0];
-  } else {
-    s0 = (r0[0] + r0[2]) + r0[1];
-    jx = (rx[0] + rx[2]) + rx[1];
-    jy = r0[2] - r0[0];
-  }
-  const float se = total<D, float>(g);
+  double s0, j[3], se;
+  conserved_sums<D, float>(f, g, s0, j, se);
   NodeMoments<float> m;
-  const float j[3] = {jx, jy, jz};
   velocity_temperature<D, float>(m, s0, j, se, k);
   return m;
 }
@@ -373,52 +391,54 @@ __device__ inline AxisG<R> axis_g(R u, R du, R u0, R T, R dT, R T0) {
   return x;
 }
 
-// Writes (f^ex - w) and (g^eq - w) for all Q populations (the equilibria with
-// the corrections d_a; d = 0 gives f^eq).  Population i of the f set goes to
-// fe[i], of the g set to ge[i].
+// Builds (f^ex - w) and (g^eq - w) (the equilibria with the corrections d_a;
+// d = 0 gives f^eq) row by row, a row being the three populations
+// jx + 3p, jx = c_x + 1, of one (c_y, c_z) pair p: the per-axis factors are
+// formed once and each row costs a few products, so a caller can relax a
+// row as soon as it is built.
 template <int D, typename R, bool DEV>
-__device__ inline void equilibria(const NodeMoments<R>& m, const R* d, const NodeConsts& k, R* fe, R* ge) {
-  const R T0 = (R)k.T0, rho0 = (R)k.rho0;
-  const R corr = m.corr;
-
+struct EqBuilder {
   AxisF<R> F[3];
   AxisG<R> G[3];
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    const R u0 = ref_u0<R>(k, a);
-    const R dP = m.dT + m.du[a] * (m.u[a] + u0) + corr * d[a];  // P - P0
-    F[a] = axis_f<R, DEV>(m.u[a], m.du[a], dP, ref_P0<R>(k, a));
-    G[a] = axis_g<R, DEV>(m.u[a], m.du[a], u0, m.T, m.dT, T0);
-  }
-  const R eps = (R)k.Cv * m.T;
-  const R deps = (R)k.Cv * m.dT;
-  const R eps0 = (R)k.Cv * T0;
-
-  // x-axis coefficients
   R hx[3], kx[3], G1[3], G2[3], G3[3], G4[3];
+  R p0y[3], b0y[3];  // y-axis reference factors (a0 = psi0)
+  R eps, deps, eps0;
+
+  __device__ inline EqBuilder(const NodeMoments<R>& m, const R* d, const NodeConsts& k) {
+    const R T0 = (R)k.T0, rho0 = (R)k.rho0;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    hx[c] = m.drho * F[0].psi[c] + (DEV ? rho0 * F[0].dpsi[c] : (R)0);
-    kx[c] = DEV ? rho0 * ref_psi0<R>(k, 0, c) : (R)0;
-    G1[c] = m.drho * G[0].a[c] + (DEV ? rho0 * G[0].da[c] : (R)0);
-    G2[c] = m.drho * G[0].b[c] + (DEV ? rho0 * G[0].db[c] : (R)0);
-    G3[c] = DEV ? rho0 * ref_psi0<R>(k, 0, c) : (R)0;
-    G4[c] = DEV ? rho0 * ref_b0<R>(k, 0, c) : (R)0;
+    for (int a = 0; a < D; ++a) {
+      const R u0 = ref_u0<R>(k, a);
+      const R dP = m.dT + m.du[a] * (m.u[a] + u0) + m.corr * d[a];  // P - P0
+      F[a] = axis_f<R, DEV>(m.u[a], m.du[a], dP, ref_P0<R>(k, a));
+      G[a] = axis_g<R, DEV>(m.u[a], m.du[a], u0, m.T, m.dT, T0);
+    }
+    eps = (R)k.Cv * m.T;
+    deps = (R)k.Cv * m.dT;
+    eps0 = (R)k.Cv * T0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      hx[c] = m.drho * F[0].psi[c] + (DEV ? rho0 * F[0].dpsi[c] : (R)0);
+      kx[c] = DEV ? rho0 * ref_psi0<R>(k, 0, c) : (R)0;
+      G1[c] = m.drho * G[0].a[c] + (DEV ? rho0 * G[0].da[c] : (R)0);
+      G2[c] = m.drho * G[0].b[c] + (DEV ? rho0 * G[0].db[c] : (R)0);
+      G3[c] = DEV ? rho0 * ref_psi0<R>(k, 0, c) : (R)0;
+      G4[c] = DEV ? rho0 * ref_b0<R>(k, 0, c) : (R)0;
+      p0y[c] = ref_psi0<R>(k, 1, c);
+      b0y[c] = ref_b0<R>(k, 1, c);
+    }
   }
 
-  constexpr int NP = (D == 3) ? 9 : 3;  // (cy, cz) pairs
-#pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    const int jy = p % 3, jz = p / 3;   // index = c + 1
+  __device__ inline void row(int p, R* fe, R* ge) const {
+    const int jy = p % 3, jz = p / 3;  // index = c + 1
     R PY, DY, A, Bs, dA, dBs;
     if (D == 3) {
       PY = F[1].psi[jy] * F[2].psi[jz];
-      const R p0y = ref_psi0<R>(k, 1, jy), b0y = ref_b0<R>(k, 1, jy);  // a0 = psi0
-      DY = F[1].dpsi[jy] * F[2].psi[jz] + p0y * F[2].dpsi[jz];
+      DY = F[1].dpsi[jy] * F[2].psi[jz] + p0y[jy] * F[2].dpsi[jz];
       A = G[1].a[jy] * G[2].a[jz];
       Bs = G[1].b[jy] * G[2].a[jz] + G[1].a[jy] * G[2].b[jz];
-      dA = G[1].da[jy] * G[2].a[jz] + p0y * G[2].da[jz];
-      dBs = G[1].db[jy] * G[2].a[jz] + b0y * G[2].da[jz] + G[1].da[jy] * G[2].b[jz] + p0y * G[2].db[jz];
+      dA = G[1].da[jy] * G[2].a[jz] + p0y[jy] * G[2].da[jz];
+      dBs = G[1].db[jy] * G[2].a[jz] + b0y[jy] * G[2].da[jz] + G[1].da[jy] * G[2].b[jz] + p0y[jy] * G[2].db[jz];
     } else {
       PY = F[1].psi[jy];
       DY = F[1].dpsi[jy];
@@ -431,17 +451,25 @@ __device__ inline void equilibria(const NodeMoments<R>& m, const R* d, const Nod
     const R V2 = deps * A + eps0 * dA + dBs;
 #pragma unroll
     for (int jx = 0; jx < 3; ++jx) {
-      const int i = jx + 3 * p;
       R fv = hx[jx] * PY;
       R gv = G1[jx] * V1 + G2[jx] * A;
       if (DEV) {
         fv += kx[jx] * DY;
         gv += G3[jx] * V2 + G4[jx] * dA;
       }
-      fe[i] = fv;
-      ge[i] = gv;
+      fe[jx] = fv;
+      ge[jx] = gv;
     }
   }
+};
+
+// All Q populations: f^ex - w into fe, g^eq - w into ge.
+template <int D, typename R, bool DEV>
+__device__ inline void equilibria(const NodeMoments<R>& m, const R* d, const NodeConsts& k, R* fe, R* ge) {
+  const EqBuilder<D, R, DEV> E(m, d, k);
+  constexpr int NR = (D == 3) ? 9 : 3;
+#pragma unroll
+  for (int p = 0; p < NR; ++p) E.row(p, fe + 3 * p, ge + 3 * p);
 }
 
 // BGK relaxation of both populations in place (Eqs. (1), (2)): f, g hold the
@@ -450,8 +478,7 @@ __device__ inline void equilibria(const NodeMoments<R>& m, const R* d, const Nod
 template <int D, typename R, bool DEV>
 __device__ inline void collide(R* f, R* g, const NodeMoments<R>& m, const R* d, const NodeConsts& k) {
   constexpr int Q = lat_q(D);
-  R fe[Q], ge[Q];
-  equilibria<D, R, DEV>(m, d, k, fe, ge);
+  const EqBuilder<D, R, DEV> E(m, d, k);
   // q* - q^eq, Eq. (46)
   R dq[3];
   dq[0] = m.u[0] * m.pn[0] + m.u[1] * m.pn[3] + (D == 3 ? m.u[2] * m.pn[4] : (R)0) + (R)0.5 * m.u[0] * d[0];
@@ -463,13 +490,14 @@ __device__ inline void collide(R* f, R* g, const NodeMoments<R>& m, const R* d, 
   R r0[NR], rx[NR], rg[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    R df[3], dg[3];
+    R fe[3], ge[3], df[3], dg[3];
+    E.row(r, fe, ge);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int i = 3 * r + c;
       const int cx = vx(i), cy = vy(i), cz = (D == 3) ? vz(i) : 0;
-      df[c] = m.omega * (fe[i] - f[i]);
-      dg[c] = m.omega1 * (ge[i] - g[i]);
+      df[c] = m.omega * (fe[c] - f[i]);
+      dg[c] = m.omega1 * (ge[c] - g[i]);
       const int c2 = cx * cx + cy * cy + cz * cz;
       if (c2 == 1) {
         const R cdq = cx ? (cx > 0 ? dq[0] : -dq[0]) : cy ? (cy > 0 ? dq[1] : -dq[1]) : (cz > 0 ? dq[2] : -dq[2]);
