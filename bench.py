@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="box edge (default 256 for turbulence3d, 1024 for shockvortex2d)")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--tile", type=str, default="", help="bx,by,chunk of the step kernel")
+    ap.add_argument("--deriv", choices=["upwind", "central"], default="upwind",
+                    help="difference scheme of the anomaly (Sec. III.A upwind, Sec. III.D.2 central)")
     ap.add_argument("--diag-every", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -143,7 +145,7 @@ def main():
     h = lbm.lbm_create(D, dims, w["gamma"], w["Pr"], w["mu"],
                        precision=lbm.LBM_FP32_DEV if word == 4 else lbm.LBM_FP64, bc=w["bc"],
                        visc_exponent=w["visc_exp"], T_ref=w["T_ref"], rho_ref=w["rho_ref"], u_ref=w["u_ref"],
-                       tile=tile)
+                       tile=tile, deriv_scheme=lbm.LBM_DERIV_CENTRAL if args.deriv == "central" else lbm.LBM_DERIV_UPWIND)
     lbm.lbm_set_stream(h, stream)
     lbm.lbm_init_fields(h, *(torch.from_numpy(a).to(dev) for a in w["fields"]))
 
@@ -195,7 +197,7 @@ def main():
 
     mlups = N * args.steps / wall / 1e6
     achieved = bytes_per_node * N / avg_kernel_s / 1e9
-    workload = w["label"].format(prec=args.precision)
+    workload = w["label"].format(prec=args.precision) + (" central-anomaly" if args.deriv == "central" else "")
     traffic = measured_traffic(workload, args.precision)
     lattice = f"D{D}Q{Q}"
     out = {
