@@ -12,6 +12,13 @@ standing Ma 1.2 shock at x = 512 with an isentropic vortex upstream); its
 FP32 working set (151 MB) fits in the 256 MB last-level cache, so its HBM
 fraction is not a roofline figure.
 
+--workload ensemble2d: 64 independent periodic D2Q9 boxes, n_x and n_y drawn
+from {64, 96, ..., 512}, 2-D decaying turbulence with Ma_t uniform in
+[0.1, 0.6] (seeds 0..63), FP32 deviations; all boxes advance by one launch
+per step (a batch), the launch shape chosen by the library's autotuner and
+the steps replayed from a captured HIP graph.  value = aggregate MLUPS over
+all boxes.
+
 One timed step = one lbm_step (one launch of the fused kernel) over the whole
 box; the diagnostics reduction runs every --diag-every steps inside the timed
 region.  Prints one JSON line (metric MLUPS) with the roofline of the step
@@ -103,12 +110,97 @@ def cpu_baseline(w, budget_s: float):
                       f"{t_total:.1f} s of stepping (initialisation excluded)"}
 
 
+def run_ensemble(args, torch, lbm, dev):
+    """The batched workload (see the module docstring)."""
+    from paper_2102_09512_amd import inputs
+
+    _log("[bench] generating the 64-box ensemble")
+    boxes = inputs.ensemble_2d(64)
+    N = sum(b["dims"][0] * b["dims"][1] for b in boxes)
+    stream = torch.cuda.current_stream(dev)
+    hs = []
+    for b in boxes:
+        h = lbm.lbm_create(2, b["dims"], 1.4, 0.7, b["mu"], precision=lbm.LBM_FP32_DEV, visc_exponent=0.76,
+                           T_ref=0.15)
+        lbm.lbm_set_stream(h, stream)
+        lbm.lbm_init_fields(h, *(torch.from_numpy(a).to(dev) for a in b["fields"]))
+        hs.append(h)
+    batch = lbm.lbm_batch_create(hs)
+    tuned_ms = lbm.lbm_batch_tune(batch, 5)
+    tile = lbm.lbm_batch_get_tile(batch)
+    _log(f"[bench] {len(hs)} boxes, {N} nodes; tuned tile {tile} ({tuned_ms:.3f} ms per step)")
+    lbm.lbm_batch_step(batch, args.warmup, 0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    lbm.lbm_batch_step(batch, args.steps, args.graph_steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = e0.elapsed_time(e1) / 1e3
+    bad = 0
+    for h in hs:
+        d = lbm.lbm_diagnostics(h)
+        bad += int(d["nonfinite"] > 0 or d["nonpositive"] > 0)
+    lbm.lbm_batch_destroy(batch)
+    for h in hs:
+        lbm.lbm_destroy(h)
+    bytes_per_node = 144
+    achieved = bytes_per_node * N / (gpu_s / args.steps) / 1e9
+    out = {
+        "metric": "aggregate MLUPS (D2Q9 batched ensemble, one launch per step)",
+        "value": round(N * args.steps / wall / 1e6, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded, no dataset)",
+        "config": {"workload": "ensemble of 64 periodic D2Q9 boxes {64..512}^2 decaying-turbulence "
+                               "Ma_t~U[0.1,0.6] fp32-storage", "lattice": "D2Q9", "boxes": len(boxes),
+                   "nodes": N, "bytes_per_node_update": bytes_per_node, "tile": list(tile),
+                   "graph_steps": args.graph_steps, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "kernel": "batch_step_kernel", "avg_step_ms": round(gpu_s / args.steps * 1e3, 4),
+                     "algorithmic_bytes_per_launch": bytes_per_node * N},
+        "kernel_source": kernel_source_hash(),
+        "boxes_with_bad_nodes": bad,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+
+        threads = oracle.num_threads()
+        nodes, t_total, used = 0, 0.0, 0
+        for b in boxes:
+            if t_total > args.cpu_seconds:
+                break
+            s = oracle.Sim(2, b["dims"], gamma=1.4, Pr=0.7, mu=b["mu"], visc_exp=0.76, T_ref=0.15)
+            s.init(*b["fields"])
+            tt = time.perf_counter()
+            s.step(5)
+            t_total += time.perf_counter() - tt
+            nodes += 5 * b["dims"][0] * b["dims"][1]
+            used += 1
+            del s
+        out["cpu_baseline"] = {"value": nodes / t_total / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+                               "sample": f"5 steps of each of the first {used} boxes, FP64, {t_total:.1f} s"}
+        out["cpu_baseline"]["gpu_speedup"] = round(out["value"] / out["cpu_baseline"]["value"], 1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["turbulence3d", "shockvortex2d"], default="turbulence3d")
+    ap.add_argument("--workload", choices=["turbulence3d", "shockvortex2d", "ensemble2d"], default="turbulence3d")
+    ap.add_argument("--graph-steps", type=int, default=50, help="ensemble2d: steps per captured HIP graph")
     ap.add_argument("--n", type=int, default=0, help="box edge (default 256 for turbulence3d, 1024 for shockvortex2d)")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--tile", type=str, default="", help="bx,by,chunk of the step kernel")
@@ -131,6 +223,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.workload == "ensemble2d":
+        print(json.dumps(run_ensemble(args, torch, lbm, dev)), flush=True)
+        return
     n = args.n or (256 if args.workload == "turbulence3d" else 1024)
     _log(f"[bench] generating the {args.workload} input, n = {n}")
     w = make_workload(args.workload, n)

@@ -145,6 +145,42 @@ const char* lbm_last_error(lbm_handle h);
    bandwidth and for scaling hardware byte counters. */
 int lbm_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
 
+/* ---- Batches: independent boxes stepped together ----------------------------
+   A batch advances several handles (boxes of any sizes, one lattice and one
+   precision, one device) by one kernel launch per time step: the launch's
+   work-groups are dealt out over all boxes' tiles through a device table, and
+   every box computes exactly what lbm_step would (same kernel body, same
+   per-box parameters, so the same result to the last bit for FP32 storage).
+   The batch does not own the handles: they stay usable on their own (init,
+   moments, diagnostics, checkpoints, lbm_step) and must outlive the batch. */
+typedef struct lbm_batch_ctx* lbm_batch;
+
+/* Builds a batch over count >= 1 distinct handles (LBM_EINVAL if they differ
+   in lattice, precision or device).  Allocates the device box table.  The
+   stream is the first handle's; the shared launch tile is the lattice's
+   default with per-box march chunks. */
+int lbm_batch_create(lbm_batch* out, const lbm_handle* boxes, int count);
+/* Frees the batch (not the handles).  NULL is accepted. */
+int lbm_batch_destroy(lbm_batch b);
+/* Stream on which lbm_batch_step orders its work (after earlier work on it). */
+int lbm_batch_set_stream(lbm_batch b, void* hip_stream);
+/* Shared launch tile {bx, by, chunk}: bx, by one of the compiled shapes of the
+   lattice (as in lbm_options.tile); chunk > 0 for every box, 0 for each box's
+   default.  LBM_EINVAL if not available.  Drops a captured graph. */
+int lbm_batch_set_tile(lbm_batch b, const int tile[3]);
+int lbm_batch_get_tile(lbm_batch b, int tile[3]);
+/* Autotuner: times every compiled shape with several march-chunk lengths over
+   reps launches each and keeps the fastest; *best_ms (may be NULL) gets its
+   time per step.  The timed launches read each box's current populations and
+   write the other buffer only, so the states are unchanged.  Synchronous. */
+int lbm_batch_tune(lbm_batch b, int reps, double* best_ms);
+/* Advances every box by n >= 0 steps.  graph_steps > 0: the launches of
+   graph_steps steps are captured once into a HIP graph (re-captured when
+   graph_steps or the tile changes) and replayed n / graph_steps times; the
+   remaining steps are launched directly.  Asynchronous.  LBM_ESTATE if a box
+   has no state, LBM_EUNSTABLE if a box's last diagnostics found a bad node. */
+int lbm_batch_step(lbm_batch b, int64_t n, int graph_steps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,8 +57,8 @@ int ensure_scratch(Ctx* c) {
   return LBM_OK;
 }
 
-void fill_params(Ctx* c) {
-  lbm::StepParams& p = c->sp;
+// Step parameters of handle c for launch tile t.
+void fill_step_params(const lbm::Ctx* c, const lbm::Tile& t, lbm::StepParams& p) {
   const int D = c->lattice;
   p.nx = (int)c->n[0];
   p.ny = (int)c->n[1];
@@ -68,9 +68,9 @@ void fill_params(Ctx* c) {
   p.ms = c->ms;
   p.plane = (int)(D == 3 ? c->n[0] * c->n[1] : c->n[0]);
   const int nm = (D == 3) ? p.nz : p.ny;
-  p.tiles_x = (p.nx + c->tile.bx - 1) / c->tile.bx;
-  p.tiles_y = (D == 3) ? (p.ny + c->tile.by - 1) / c->tile.by : 1;
-  p.chunk_len = c->tile.chunk;
+  p.tiles_x = (p.nx + t.bx - 1) / t.bx;
+  p.tiles_y = (D == 3) ? (p.ny + t.by - 1) / t.by : 1;
+  p.chunk_len = t.chunk;
   p.chunks = (nm + p.chunk_len - 1) / p.chunk_len;
   p.nblocks = p.tiles_x * p.tiles_y * p.chunks;
   p.deriv = c->opt.deriv_scheme;
@@ -128,6 +128,8 @@ void fill_params(Ctx* c) {
     }
   }
 }
+
+void fill_params(Ctx* c) { fill_step_params(c, c->tile, c->sp); }
 
 bool fields_valid_host(const double* rho, const double* u, const double* T, int64_t N, int D) {
   for (int64_t n = 0; n < N; ++n) {
@@ -413,6 +415,269 @@ int lbm_device_copy(void* dst, const void* src, size_t bytes, void* stream) {
   if (bytes % 16) return fail(LBM_EINVAL, "lbm_device_copy: bytes must be a multiple of 16");
   if (((uintptr_t)dst | (uintptr_t)src) % 16) return fail(LBM_EINVAL, "lbm_device_copy: pointers must be 16-byte aligned");
   HIP_OR_FAIL(lbm::launch_copy(dst, src, bytes, static_cast<hipStream_t>(stream)), "copy kernel");
+  return LBM_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Batches: several handles stepped by one launch per step
+// ---------------------------------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+using Batch = lbm_batch_ctx;
+
+// Step parameters of every box for the batch tile, block offsets, upload of
+// the table (synchronous on the caller's stream); drops a captured graph.
+int batch_layout(Batch* b) {
+  int64_t total = 0;
+  for (size_t i = 0; i < b->boxes.size(); ++i) {
+    const lbm::Ctx* c = b->boxes[i];
+    lbm::Tile t = b->tile;
+    const int64_t nm = c->lattice == 3 ? c->n[2] : c->n[1];
+    if (t.chunk <= 0) t.chunk = lbm::default_tile(c->lattice, c->precision, c->n).chunk;
+    if (t.chunk > nm) t.chunk = (int)nm;
+    lbm::BoxEntry& e = b->host[i];
+    fill_step_params(c, t, e.p);
+    e.buf[0] = c->buf[0];
+    e.buf[1] = c->buf[1];
+    e.cur = c->cur;
+    e.block_start = (int)total;
+    total += e.p.nblocks;
+    b->cur_dev[i] = c->cur;
+  }
+  if (total > INT32_MAX) return fail(LBM_EINVAL, "lbm_batch: too many work-groups");
+  b->total_blocks = (int)total;
+  HIP_OR_FAIL(hipMemcpyAsync(b->table, b->host.data(), sizeof(lbm::BoxEntry) * b->host.size(), hipMemcpyHostToDevice,
+                             b->user_stream),
+              "upload box table");
+  HIP_OR_FAIL(hipStreamSynchronize(b->user_stream), "hipStreamSynchronize");
+  if (b->exec) {
+    HIP_OR_FAIL(hipGraphExecDestroy(b->exec), "hipGraphExecDestroy");
+    b->exec = nullptr;
+    b->graph_steps = 0;
+  }
+  return LBM_OK;
+}
+
+int batch_select_device(Batch* b) {
+  int cur = -1;
+  HIP_OR_FAIL(hipGetDevice(&cur), "hipGetDevice");
+  if (cur != b->device) HIP_OR_FAIL(hipSetDevice(b->device), "hipSetDevice");
+  return LBM_OK;
+}
+
+// Records graph_steps batched steps on the batch's own stream.
+int batch_capture(Batch* b, int graph_steps) {
+  if (b->exec) {
+    HIP_OR_FAIL(hipGraphExecDestroy(b->exec), "hipGraphExecDestroy");
+    b->exec = nullptr;
+  }
+  HIP_OR_FAIL(hipStreamBeginCapture(b->own_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  hipError_t e = hipSuccess;
+  for (int j = 0; j < graph_steps && e == hipSuccess; ++j) e = lbm::launch_batch_step(*b, b->own_stream, j & 1);
+  if (e == hipSuccess && (graph_steps & 1)) e = lbm::launch_toggle(*b, b->own_stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(b->own_stream, &graph);
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return hip_fail(e, "batched step kernel (capture)");
+  }
+  if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    b->exec = nullptr;
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  b->graph_steps = graph_steps;
+  return LBM_OK;
+}
+
+// Supported shared tiles (bx, by) of a lattice.
+std::vector<lbm::Tile> batch_candidates(int D) {
+  std::vector<lbm::Tile> v;
+  if (D == 3) {
+    for (int chunk : {16, 32, 64, 128, 256}) {
+      v.push_back({64, 4, chunk});
+      v.push_back({32, 8, chunk});
+    }
+  } else {
+    for (int bx : {64, 128, 256})
+      for (int chunk : {4, 8, 16, 32}) v.push_back({bx, 1, chunk});
+  }
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_create(lbm_batch* out, const lbm_handle* boxes, int count) {
+  if (!out) return fail(LBM_EINVAL, "lbm_batch_create: out is NULL");
+  *out = nullptr;
+  if (!boxes || count < 1) return fail(LBM_EINVAL, "lbm_batch_create: need at least one handle");
+  for (int i = 0; i < count; ++i) {
+    if (!boxes[i]) return fail(LBM_EINVAL, "lbm_batch_create: NULL handle");
+    if (boxes[i]->lattice != boxes[0]->lattice || boxes[i]->precision != boxes[0]->precision ||
+        boxes[i]->device != boxes[0]->device)
+      return fail(LBM_EINVAL, "lbm_batch_create: handles differ in lattice, precision or device");
+    for (int j = 0; j < i; ++j)
+      if (boxes[j] == boxes[i]) return fail(LBM_EINVAL, "lbm_batch_create: a handle appears twice");
+  }
+  Batch* b = new (std::nothrow) lbm_batch_ctx();
+  if (!b) return fail(LBM_ENOMEM, "lbm_batch_create: host allocation failed");
+  b->lattice = boxes[0]->lattice;
+  b->precision = boxes[0]->precision;
+  b->device = boxes[0]->device;
+  b->boxes.assign(boxes, boxes + count);
+  b->host.resize(count);
+  b->cur_dev.assign(count, 0);
+  b->user_stream = boxes[0]->stream;
+  const lbm::Tile t0 = lbm::default_tile(b->lattice, b->precision, boxes[0]->n);
+  b->tile = {t0.bx, t0.by, 0};
+  int rc = batch_select_device(b);
+  hipError_t e = hipSuccess;
+  if (rc == LBM_OK) e = hipMalloc(&b->table, sizeof(lbm::BoxEntry) * (size_t)count);
+  if (rc == LBM_OK && e == hipSuccess) e = hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking);
+  if (rc == LBM_OK && e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+  if (rc == LBM_OK && e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+  if (rc == LBM_OK && e != hipSuccess) rc = hip_fail(e, "lbm_batch_create");
+  if (rc == LBM_OK) rc = batch_layout(b);
+  if (rc != LBM_OK) {
+    lbm_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+int lbm_batch_destroy(lbm_batch b) {
+  if (!b) return LBM_OK;
+  (void)batch_select_device(b);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->own_stream) (void)hipStreamSynchronize(b->own_stream);
+  if (b->table) (void)hipFree(b->table);
+  if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  delete b;
+  return LBM_OK;
+}
+
+int lbm_batch_set_stream(lbm_batch b, void* hip_stream) {
+  if (!b) return fail(LBM_EINVAL, "lbm_batch_set_stream: NULL batch");
+  b->user_stream = static_cast<hipStream_t>(hip_stream);
+  return LBM_OK;
+}
+
+int lbm_batch_set_tile(lbm_batch b, const int tile[3]) {
+  if (!b || !tile) return fail(LBM_EINVAL, "lbm_batch_set_tile: NULL argument");
+  const lbm::Tile t{tile[0], b->lattice == LBM_D2Q9 && tile[1] == 0 ? 1 : tile[1], tile[2] < 0 ? -1 : tile[2]};
+  if (t.chunk < 0 || !lbm::tile_supported(b->lattice, b->precision, {t.bx, t.by, t.chunk > 0 ? t.chunk : 1}))
+    return fail(LBM_EINVAL, "lbm_batch_set_tile: launch tile not available");
+  int rc = batch_select_device(b);
+  if (rc != LBM_OK) return rc;
+  b->tile = t;
+  return batch_layout(b);
+}
+
+int lbm_batch_get_tile(lbm_batch b, int tile[3]) {
+  if (!b || !tile) return fail(LBM_EINVAL, "lbm_batch_get_tile: NULL argument");
+  tile[0] = b->tile.bx;
+  tile[1] = b->tile.by;
+  tile[2] = b->tile.chunk;
+  return LBM_OK;
+}
+
+int lbm_batch_tune(lbm_batch b, int reps, double* best_ms) {
+  if (!b) return fail(LBM_EINVAL, "lbm_batch_tune: NULL batch");
+  if (reps < 1) return fail(LBM_EINVAL, "lbm_batch_tune: reps must be >= 1");
+  for (lbm::Ctx* c : b->boxes)
+    if (!c->initialised) return fail(LBM_ESTATE, "lbm_batch_tune: a box has no state (lbm_init_fields)");
+  int rc = batch_select_device(b);
+  if (rc != LBM_OK) return rc;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  HIP_OR_FAIL(hipEventCreate(&t0), "hipEventCreate");
+  hipError_t e = hipEventCreate(&t1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(t0);
+    return hip_fail(e, "hipEventCreate");
+  }
+  // Every timed launch reads each box's current buffer and writes the other
+  // one (flip 0, no toggle), so the states are left as they were.
+  lbm::Tile best = b->tile;
+  float best_t = -1.0f;
+  for (const lbm::Tile& cand : batch_candidates(b->lattice)) {
+    if (!lbm::tile_supported(b->lattice, b->precision, cand)) continue;
+    b->tile = cand;
+    if ((rc = batch_layout(b)) != LBM_OK) break;
+    if ((e = lbm::launch_batch_step(*b, b->user_stream, 0)) != hipSuccess) break;
+    if ((e = hipEventRecord(t0, b->user_stream)) != hipSuccess) break;
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = lbm::launch_batch_step(*b, b->user_stream, 0);
+    if (e != hipSuccess || (e = hipEventRecord(t1, b->user_stream)) != hipSuccess) break;
+    if ((e = hipEventSynchronize(t1)) != hipSuccess) break;
+    float ms = 0.0f;
+    if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
+    if (best_t < 0.0f || ms < best_t) {
+      best_t = ms;
+      best = cand;
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  b->tile = best;
+  const int rc2 = batch_layout(b);
+  if (rc != LBM_OK) return rc;
+  if (e != hipSuccess) return hip_fail(e, "lbm_batch_tune");
+  if (rc2 != LBM_OK) return rc2;
+  if (best_ms) *best_ms = best_t / reps;
+  return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch b, int64_t n, int graph_steps) {
+  if (!b) return fail(LBM_EINVAL, "lbm_batch_step: NULL batch");
+  if (n < 0 || graph_steps < 0) return fail(LBM_EINVAL, "lbm_batch_step: negative count");
+  for (lbm::Ctx* c : b->boxes) {
+    if (!c->initialised) return fail(LBM_ESTATE, "lbm_batch_step: a box has no state (lbm_init_fields)");
+    if (c->unstable) return fail(LBM_EUNSTABLE, "lbm_batch_step: a box is unstable (see lbm_diagnostics)");
+  }
+  if (n == 0) return LBM_OK;
+  int rc = batch_select_device(b);
+  if (rc != LBM_OK) return rc;
+  // a box stepped on its own since the last batched step: refresh the table
+  for (size_t i = 0; i < b->boxes.size(); ++i)
+    if (b->boxes[i]->cur != b->cur_dev[i]) {
+      if ((rc = batch_layout(b)) != LBM_OK) return rc;
+      break;
+    }
+  hipStream_t s = b->user_stream;
+  int64_t done = 0;
+  int flips = 0;
+  if (graph_steps > 0 && n >= graph_steps) {
+    if (!b->exec || b->graph_steps != graph_steps)
+      if ((rc = batch_capture(b, graph_steps)) != LBM_OK) return rc;
+    HIP_OR_FAIL(hipEventRecord(b->ev_in, s), "hipEventRecord");
+    HIP_OR_FAIL(hipStreamWaitEvent(b->own_stream, b->ev_in, 0), "hipStreamWaitEvent");
+    const int64_t reps = n / graph_steps;
+    for (int64_t r = 0; r < reps; ++r) HIP_OR_FAIL(hipGraphLaunch(b->exec, b->own_stream), "hipGraphLaunch");
+    HIP_OR_FAIL(hipEventRecord(b->ev_out, b->own_stream), "hipEventRecord");
+    HIP_OR_FAIL(hipStreamWaitEvent(s, b->ev_out, 0), "hipStreamWaitEvent");
+    done = reps * graph_steps;
+    flips = (int)((graph_steps & 1) * (reps & 1));
+  }
+  const int64_t rest = n - done;
+  for (int64_t j = 0; j < rest; ++j) HIP_OR_FAIL(lbm::launch_batch_step(*b, s, (int)(j & 1)), "batched step kernel");
+  if (rest & 1) HIP_OR_FAIL(lbm::launch_toggle(*b, s), "toggle kernel");
+  flips ^= (int)(rest & 1);
+  for (size_t i = 0; i < b->boxes.size(); ++i) {
+    lbm::Ctx* c = b->boxes[i];
+    c->cur ^= flips;
+    c->step += n;
+    b->cur_dev[i] = c->cur;
+  }
   return LBM_OK;
 }
 

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "lbm.h"
 
@@ -67,6 +68,30 @@ struct Ctx {
 
 constexpr int kNumDiag = 21;  // slots of the diagnostic reduction (see lbm_kernels.hip)
 
+// One box of a batched launch (an entry of the device box table).
+struct BoxEntry {
+  StepParams p;       // the box's step parameters for the batch tile
+  void* buf[2];       // the box's population buffers
+  int cur;            // buffer holding the box's state when the launch sequence starts
+  int block_start;    // first logical work-group of the box in the launch
+};
+
+// Several handles of one lattice and precision stepped by one launch per step.
+struct Batch {
+  int lattice = 0, precision = 0, device = 0;
+  std::vector<Ctx*> boxes;
+  std::vector<BoxEntry> host;      // host image of the table
+  BoxEntry* table = nullptr;       // device table
+  std::vector<int> cur_dev;        // cur of each box as the device table holds it
+  int total_blocks = 0;
+  Tile tile{};                     // bx, by shared by all boxes; chunk 0 = per-box default
+  hipStream_t user_stream = nullptr;
+  hipStream_t own_stream = nullptr;  // graph replays run here
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t exec = nullptr;     // captured sequence of graph_steps steps
+  int graph_steps = 0;
+};
+
 // ---- launchers (lbm_kernels.hip) -------------------------------------------
 hipError_t launch_step(const Ctx& c, const void* src, void* dst);
 hipError_t launch_init(const Ctx& c, const double* rho, const double* u, const double* T, void* dst);
@@ -79,6 +104,8 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 // Internal population layout <-> the ABI state layout (2Q arrays of N values).
 hipError_t launch_pack(const Ctx& c, const void* pops, void* state);
 hipError_t launch_unpack(const Ctx& c, const void* state, void* pops);
+hipError_t launch_batch_step(const Batch& b, hipStream_t s, int flip);
+hipError_t launch_toggle(const Batch& b, hipStream_t s);
 // Default launch tile for a lattice/precision and whether a tile is available.
 Tile default_tile(int D, int precision, const int64_t n[3]);
 bool tile_supported(int D, int precision, const Tile& t);
@@ -87,3 +114,4 @@ bool tile_supported(int D, int precision, const Tile& t);
 
 // The opaque handle type of the C ABI.
 struct lbm_ctx : public lbm::Ctx {};
+struct lbm_batch_ctx : public lbm::Batch {};

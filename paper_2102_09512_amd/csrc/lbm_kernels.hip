@@ -200,9 +200,10 @@ __device__ inline NodeMoments<R> pulled_moments_batched(const __amdgpu_buffer_rs
   return m;
 }
 
+// One work-group's share of a step: tile lb (x fastest, then y, then the
+// march chunk) of the box described by p.
 template <int D, bool DEV, typename S, int BX, int BY>
-__global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src, S* __restrict__ dst,
-                                                      const StepParams p) {
+__device__ inline void step_tile(const S* __restrict__ src, S* __restrict__ dst, const StepParams& p, int lb) {
   using R = typename StoreOf<S>::R;
   constexpr int Q = lat_q(D);
   constexpr int NHALO = (D == 3) ? 2 * BX + 2 * BY : 2;
@@ -213,10 +214,6 @@ __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src,
 
   const NodeConsts k = node_consts(p);
 
-  // XCD-aware logical block
-  const int b = blockIdx.x;
-  const int q8 = p.nblocks >> 3, r8 = p.nblocks & 7, xcd = b & 7;
-  const int lb = xcd * q8 + min(xcd, r8) + (b >> 3);
   const int tx = lb % p.tiles_x;
   const int rest = lb / p.tiles_x;
   const int ty = (D == 3) ? rest % p.tiles_y : 0;
@@ -426,6 +423,44 @@ __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src,
       mo0 = mo1;
     }
   }
+}
+
+// XCD-aware logical block: consecutive hardware block ids go round the eight
+// XCDs, so logical blocks are renumbered such that each XCD runs one
+// contiguous range (neighbouring tiles then share an L2).
+__device__ inline int xcd_logical_block(int b, int nblocks) {
+  const int q8 = nblocks >> 3, r8 = nblocks & 7, xcd = b & 7;
+  return xcd * q8 + min(xcd, r8) + (b >> 3);
+}
+
+template <int D, bool DEV, typename S, int BX, int BY>
+__global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src, S* __restrict__ dst,
+                                                      const StepParams p) {
+  step_tile<D, DEV, S, BX, BY>(src, dst, p, xcd_logical_block(blockIdx.x, p.nblocks));
+}
+
+// Several boxes in one launch: logical block g belongs to the last box whose
+// first block is <= g; that box's current buffer (cur ^ flip) is the source.
+template <int D, bool DEV, typename S, int BX, int BY>
+__global__ void __launch_bounds__(BX* BY) batch_step_kernel(const BoxEntry* __restrict__ table, int nboxes,
+                                                            int total_blocks, int flip) {
+  const int g = xcd_logical_block(blockIdx.x, total_blocks);
+  int lo = 0, hi = nboxes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (table[mid].block_start <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  const BoxEntry& e = table[lo];
+  const int par = e.cur ^ flip;
+  step_tile<D, DEV, S, BX, BY>(static_cast<const S*>(e.buf[par]), static_cast<S*>(e.buf[par ^ 1]), e.p,
+                               g - e.block_start);
+}
+
+// After an odd number of batched steps every box's current buffer changes.
+__global__ void __launch_bounds__(64) toggle_cur_kernel(BoxEntry* __restrict__ table, int nboxes) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nboxes) table[i].cur ^= 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -697,6 +732,43 @@ hipError_t launch_step(const Ctx& c, const void* src, void* dst) {
   }
   if (c.precision == LBM_FP64) return dispatch_tile<2, false, double>(c, src, dst);
   return dispatch_tile<2, true, float>(c, src, dst);
+}
+
+template <int D, bool DEV, typename S, int BX, int BY>
+static hipError_t launch_batch_t(const Batch& b, hipStream_t s, int flip) {
+  hipLaunchKernelGGL((batch_step_kernel<D, DEV, S, BX, BY>), dim3(b.total_blocks), dim3(BX * BY), 0, s, b.table,
+                     (int)b.boxes.size(), b.total_blocks, flip);
+  return hipGetLastError();
+}
+
+template <int D, bool DEV, typename S>
+static hipError_t dispatch_batch(const Batch& b, hipStream_t s, int flip) {
+  const Tile& t = b.tile;
+  if constexpr (D == 3) {
+    if (t.bx == 64 && t.by == 4) return launch_batch_t<D, DEV, S, 64, 4>(b, s, flip);
+    if (t.bx == 64 && t.by == 8) return launch_batch_t<D, DEV, S, 64, 8>(b, s, flip);
+    if (t.bx == 32 && t.by == 8) return launch_batch_t<D, DEV, S, 32, 8>(b, s, flip);
+  } else {
+    if (t.bx == 64) return launch_batch_t<D, DEV, S, 64, 1>(b, s, flip);
+    if (t.bx == 128) return launch_batch_t<D, DEV, S, 128, 1>(b, s, flip);
+    if (t.bx == 256) return launch_batch_t<D, DEV, S, 256, 1>(b, s, flip);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_step(const Batch& b, hipStream_t s, int flip) {
+  if (b.lattice == 3) {
+    if (b.precision == LBM_FP64) return dispatch_batch<3, false, double>(b, s, flip);
+    return dispatch_batch<3, true, float>(b, s, flip);
+  }
+  if (b.precision == LBM_FP64) return dispatch_batch<2, false, double>(b, s, flip);
+  return dispatch_batch<2, true, float>(b, s, flip);
+}
+
+hipError_t launch_toggle(const Batch& b, hipStream_t s) {
+  const int n = (int)b.boxes.size();
+  hipLaunchKernelGGL(toggle_cur_kernel, dim3((n + 63) / 64), dim3(64), 0, s, b.table, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_init(const Ctx& c, const double* rho, const double* u, const double* T, void* dst) {

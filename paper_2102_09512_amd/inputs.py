@@ -170,6 +170,82 @@ def turbulence_viscosity(n, k0_index=4, Ma_t=0.5, T0=0.15, rho0=1.0, gamma=1.4, 
     return rho0 * u_rms * lam / Re_lambda
 
 
+def turbulence_box2d(nx, ny, seed, k0_index=4, Ma_t=0.5, T0=0.15, rho0=1.0, gamma=1.4):
+    """2-D solenoidal random velocity on a periodic nx x ny box with the shell
+    spectrum E(k) = A k^4 exp(-2 (k/k0)^2) in physical wave number
+    k = 2 pi (i/nx, j/ny): shells of width 2 pi / L and k0 = k0_index 2 pi / L
+    with L = min(nx, ny) (the box fits k0_index wavelengths of the peak in
+    both directions).  Same synthesis as turbulence(): random solenoidal
+    directions and phases, exact per-shell energy, Hermitian, scaled so that
+    sqrt(<u.u>) = Ma_t sqrt(gamma T0).  Returns rho, u, T with shapes
+    (1, ny, nx) and (2, 1, ny, nx)."""
+    rng = np.random.default_rng(seed)
+    L = min(nx, ny)
+    ix = np.fft.fftfreq(nx, d=1.0 / nx)
+    iy = np.fft.fftfreq(ny, d=1.0 / ny)
+    IX, IY = np.meshgrid(ix, iy, indexing="xy")  # arrays (ny, nx)
+    KX, KY = IX / nx, IY / ny                      # wave number / (2 pi)
+    kmag = np.sqrt(KX ** 2 + KY ** 2)
+    shell = np.rint(kmag * L).astype(np.int64)      # in units of 2 pi / L
+    a = rng.standard_normal((2, ny, nx)) + 1j * rng.standard_normal((2, ny, nx))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        kdota = (KX * a[0] + KY * a[1]) / np.where(kmag > 0, kmag ** 2, 1.0)
+    a = a - np.stack([KX, KY]) * kdota
+    norm = np.sqrt((np.abs(a) ** 2).sum(0))
+    a = a / np.where(norm > 0, norm, 1.0)
+    kk = np.arange(shell.max() + 1, dtype=np.float64)
+    E = kk ** 4 * np.exp(-2.0 * (kk / k0_index) ** 2)
+    count = np.bincount(shell.ravel(), minlength=kk.size).astype(np.float64)
+    amp = np.sqrt(np.where(count > 0, 2.0 * E / np.maximum(count, 1.0), 0.0)[shell])
+    nyq = np.zeros((ny, nx), dtype=bool)
+    if nx % 2 == 0:
+        nyq |= np.abs(IX) == nx // 2
+    if ny % 2 == 0:
+        nyq |= np.abs(IY) == ny // 2
+    amp = np.where(nyq | (kmag == 0), 0.0, amp)
+    uh = a * amp
+    # Hermitian: canonical half (j > 0, or j == 0 and i > 0), the rest mirrored
+    jj, ii = np.indices((ny, nx))
+    canon = (IY > 0) | ((IY == 0) & (IX > 0))
+    mirror = uh[:, (-jj) % ny, (-ii) % nx]
+    uh = np.where(canon[None], uh, np.conj(mirror))
+    u = np.fft.ifft2(uh, axes=(1, 2)).real
+    scale = Ma_t * math.sqrt(gamma * T0) / math.sqrt((u ** 2).sum(0).mean())
+    u = (u * scale)[:, None, :, :]
+    rho = np.full((1, ny, nx), rho0)
+    T = np.full((1, ny, nx), T0)
+    return rho, np.ascontiguousarray(u), T
+
+
+def taylor_viscosity(u, rho0=1.0, Re_lambda=72.0):
+    """mu_0 = <rho> u_rms lambda / Re_lambda with lambda measured on the field:
+    lambda = sqrt(<u_x^2> / <(d_x u_x)^2>) (spectral x-derivative) and
+    u_rms = sqrt(<u.u> / D).  u has shape (D, ..., nx) with x the last axis."""
+    D = u.shape[0]
+    nx = u.shape[-1]
+    kx = 2.0 * math.pi * np.fft.fftfreq(nx, d=1.0)
+    dudx = np.fft.ifft(1j * kx * np.fft.fft(u[0], axis=-1), axis=-1).real
+    lam = math.sqrt((u[0] ** 2).mean() / (dudx ** 2).mean())
+    u_rms = math.sqrt((u ** 2).sum(0).mean() / D)
+    return rho0 * u_rms * lam / Re_lambda
+
+
+def ensemble_2d(count=64, sizes=tuple(range(64, 513, 32)), Ma_range=(0.1, 0.6), T0=0.15, Re_lambda=72.0):
+    """The batched workload: count independent periodic D2Q9 boxes; box s
+    draws n_x, n_y (independently, uniformly from sizes) and Ma_t (uniformly
+    in Ma_range) from seed s and carries turbulence_box2d(seed = s) with mu_0
+    from its own measured Taylor microscale."""
+    boxes = []
+    for s in range(count):
+        r = np.random.default_rng(s)
+        nx, ny = int(r.choice(sizes)), int(r.choice(sizes))
+        ma = float(r.uniform(*Ma_range))
+        rho, u, T = turbulence_box2d(nx, ny, seed=s, Ma_t=ma, T0=T0)
+        boxes.append(dict(seed=s, dims=(nx, ny), Ma_t=ma, fields=(rho, u, T),
+                          mu=taylor_viscosity(u[:, 0], Re_lambda=Re_lambda)))
+    return boxes
+
+
 # ---------------------------------------------------------------------------
 # Small test fields
 # ---------------------------------------------------------------------------

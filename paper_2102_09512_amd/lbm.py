@@ -73,8 +73,17 @@ def _load():
     L.lbm_last_error.argtypes = [vp]
     L.lbm_last_error.restype = C.c_char_p
     L.lbm_device_copy.argtypes = [vp, vp, C.c_size_t, vp]
+    L.lbm_batch_create.argtypes = [C.POINTER(vp), C.POINTER(vp), C.c_int]
+    L.lbm_batch_destroy.argtypes = [vp]
+    L.lbm_batch_set_stream.argtypes = [vp, vp]
+    L.lbm_batch_set_tile.argtypes = [vp, C.POINTER(C.c_int)]
+    L.lbm_batch_get_tile.argtypes = [vp, C.POINTER(C.c_int)]
+    L.lbm_batch_tune.argtypes = [vp, C.c_int, dp]
+    L.lbm_batch_step.argtypes = [vp, i64, C.c_int]
     for name in ("lbm_create", "lbm_destroy", "lbm_set_stream", "lbm_init_fields", "lbm_step", "lbm_moments",
-                 "lbm_diagnostics", "lbm_get_state", "lbm_set_state", "lbm_device_copy"):
+                 "lbm_diagnostics", "lbm_get_state", "lbm_set_state", "lbm_device_copy", "lbm_batch_create",
+                 "lbm_batch_destroy", "lbm_batch_set_stream", "lbm_batch_set_tile", "lbm_batch_get_tile",
+                 "lbm_batch_tune", "lbm_batch_step"):
         getattr(L, name).restype = C.c_int
     return L
 
@@ -238,3 +247,45 @@ def lbm_device_copy(dst, src, nbytes: int, stream=None) -> int:
 def raw():
     """The ctypes library object (for the ABI tests)."""
     return _L
+
+
+# ---- batches -----------------------------------------------------------------
+
+def lbm_batch_create(handles) -> int:
+    """A batch over the given handles (which must outlive it)."""
+    arr = (C.c_void_p * len(handles))(*handles)
+    b = C.c_void_p()
+    _check(_L.lbm_batch_create(C.byref(b), arr, len(handles)))
+    return b.value
+
+
+def lbm_batch_destroy(b) -> int:
+    return _check(_L.lbm_batch_destroy(b))
+
+
+def lbm_batch_set_stream(b, stream) -> int:
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    return _check(_L.lbm_batch_set_stream(b, stream))
+
+
+def lbm_batch_set_tile(b, tile) -> int:
+    t = (C.c_int * 3)(*[int(v) for v in tile])
+    return _check(_L.lbm_batch_set_tile(b, t))
+
+
+def lbm_batch_get_tile(b):
+    t = (C.c_int * 3)()
+    _check(_L.lbm_batch_get_tile(b, t))
+    return tuple(t)
+
+
+def lbm_batch_tune(b, reps: int = 5) -> float:
+    """Runs the autotuner; returns the best time per step in ms."""
+    ms = C.c_double()
+    _check(_L.lbm_batch_tune(b, int(reps), C.byref(ms)))
+    return ms.value
+
+
+def lbm_batch_step(b, n: int = 1, graph_steps: int = 0) -> int:
+    return _check(_L.lbm_batch_step(b, int(n), int(graph_steps)))

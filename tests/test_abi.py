@@ -81,3 +81,15 @@ def test_null_handle_calls_fail_cleanly(lbm):
     assert L.lbm_step_count(None) == -1
     assert L.lbm_state_bytes(None) == 0
     assert L.lbm_device_copy(None, None, 16, None) == lbm.LBM_EINVAL
+
+
+def test_batch_null_arguments_fail_cleanly(lbm):
+    L = lbm.raw()
+    import ctypes as C
+    out = C.c_void_p()
+    assert L.lbm_batch_create(C.byref(out), None, 0) == lbm.LBM_EINVAL
+    assert out.value is None
+    assert L.lbm_batch_destroy(None) == lbm.LBM_OK
+    assert L.lbm_batch_step(None, 1, 0) == lbm.LBM_EINVAL
+    assert L.lbm_batch_tune(None, 1, None) == lbm.LBM_EINVAL
+    assert L.lbm_batch_set_stream(None, None) == lbm.LBM_EINVAL

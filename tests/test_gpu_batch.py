@@ -1,0 +1,187 @@
+"""Batches of independent boxes stepped by one launch per step: every box must
+end exactly where lbm_step takes it (same kernel body and parameters), with
+and without HIP-graph replay, across replays interleaved with the program's
+own work, after the autotuner, and when boxes are also stepped on their own."""
+import numpy as np
+import pytest
+
+from paper_2102_09512_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _lbm():
+    from paper_2102_09512_amd import lbm
+
+    return lbm
+
+
+def _boxes_2d(count, seed0=0):
+    """Uneven, resolved boxes (the spectral peak has at least 16 nodes per
+    wavelength) at subsonic turbulent Mach numbers."""
+    sizes = tuple(range(64, 161, 32))
+    boxes = []
+    for s in range(count):
+        r = np.random.default_rng(seed0 + s)
+        nx, ny = int(r.choice(sizes)), int(r.choice(sizes))
+        ma = float(r.uniform(0.1, 0.4))
+        rho, u, T = I.turbulence_box2d(nx, ny, seed=seed0 + s, Ma_t=ma, T0=0.15)
+        boxes.append(dict(dims=(nx, ny), fields=(rho, u, T), mu=I.taylor_viscosity(u[:, 0])))
+    return boxes
+
+
+def _make(lbm, boxes, precision, D=2):
+    hs = []
+    for b in boxes:
+        dims = b["dims"] if D == 2 else b["dims"]
+        h = lbm.lbm_create(D, dims, 1.4, 0.7, b["mu"], precision=precision, visc_exponent=0.76, T_ref=0.15)
+        lbm.lbm_set_stream(h, torch.cuda.current_stream())
+        lbm.lbm_init_fields(h, *(torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in b["fields"]))
+        hs.append(h)
+    return hs
+
+
+def _states(lbm, hs, fp32):
+    out = []
+    for h in hs:
+        nb = lbm.lbm_state_bytes(h)
+        t = torch.empty(nb // (4 if fp32 else 8), dtype=torch.float32 if fp32 else torch.float64, device="cuda")
+        lbm.lbm_get_state(h, t)
+        torch.cuda.synchronize()
+        out.append(t.cpu().numpy())
+    return out
+
+
+def _same(a, b):
+    for x, y in zip(a, b):
+        assert np.isfinite(x).all() and np.isfinite(y).all(), "a box blew up"
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("fp32", [True, False])
+def test_batch_equals_individual_steps(fp32):
+    lbm = _lbm()
+    prec = lbm.LBM_FP32_DEV if fp32 else lbm.LBM_FP64
+    boxes = _boxes_2d(7)
+    print(f"[gpu case] batch of {len(boxes)} D2Q9 boxes {[b['dims'] for b in boxes]} fp32={fp32}", flush=True)
+    ref, bat = _make(lbm, boxes, prec), _make(lbm, boxes, prec)
+    b = lbm.lbm_batch_create(bat)
+    try:
+        for h in ref:
+            lbm.lbm_step(h, 37)
+        lbm.lbm_batch_step(b, 37)
+        assert all(lbm.lbm_step_count(h) == 37 for h in bat)
+        assert _same(_states(lbm, ref, fp32), _states(lbm, bat, fp32))
+    finally:
+        lbm.lbm_batch_destroy(b)
+        for h in ref + bat:
+            lbm.lbm_destroy(h)
+
+
+def test_batch_graph_replays_interleaved_with_other_work():
+    """Graph replays (even and odd captured lengths, remainders launched
+    directly), with diagnostics, a single-box step and host synchronisation
+    in between; every stage equals the individually stepped boxes."""
+    lbm = _lbm()
+    boxes = _boxes_2d(5, seed0=20)
+    ref, bat = _make(lbm, boxes, lbm.LBM_FP32_DEV), _make(lbm, boxes, lbm.LBM_FP32_DEV)
+    b = lbm.lbm_batch_create(bat)
+    try:
+        total = 0
+        for n, g in [(10, 4), (9, 3), (12, 4), (7, 3), (5, 0)]:
+            print(f"[gpu case] batch graph: {n} steps, graph of {g}", flush=True)
+            lbm.lbm_batch_step(b, n, g)
+            for h in ref:
+                lbm.lbm_step(h, n)
+            total += n
+            lbm.lbm_diagnostics(bat[0])
+            torch.cuda.synchronize()
+            assert _same(_states(lbm, ref, True), _states(lbm, bat, True)), (n, g)
+            # one box stepped on its own between batched steps
+            lbm.lbm_step(bat[1], 1)
+            lbm.lbm_step(ref[1], 1)
+        assert lbm.lbm_step_count(bat[0]) == total and lbm.lbm_step_count(bat[1]) == total + 5
+    finally:
+        lbm.lbm_batch_destroy(b)
+        for h in ref + bat:
+            lbm.lbm_destroy(h)
+
+
+@pytest.mark.parametrize("fp32", [True, False])
+def test_autotuner_keeps_states_and_tuned_steps_match(fp32):
+    lbm = _lbm()
+    prec = lbm.LBM_FP32_DEV if fp32 else lbm.LBM_FP64
+    boxes = _boxes_2d(6, seed0=40)
+    ref, bat = _make(lbm, boxes, prec), _make(lbm, boxes, prec)
+    b = lbm.lbm_batch_create(bat)
+    try:
+        lbm.lbm_batch_step(b, 3)
+        for h in ref:
+            lbm.lbm_step(h, 3)
+        before = _states(lbm, bat, fp32)
+        ms = lbm.lbm_batch_tune(b, 3)
+        tile = lbm.lbm_batch_get_tile(b)
+        print(f"[gpu case] tuned tile {tile}, {ms:.4f} ms per step", flush=True)
+        assert tile[0] in (64, 128, 256) and tile[1] == 1 and tile[2] in (4, 8, 16, 32)
+        assert _same(before, _states(lbm, bat, fp32))  # tuning leaves the states alone
+        lbm.lbm_batch_step(b, 20, 5)
+        for h in ref:
+            lbm.lbm_step(h, 20)
+        for x, y in zip(_states(lbm, ref, fp32), _states(lbm, bat, fp32)):
+            # another tile only changes which thread does what (rounding-level at most)
+            assert np.abs(x - y).max() <= (1e-6 if fp32 else 1e-13) * np.abs(x).max()
+    finally:
+        lbm.lbm_batch_destroy(b)
+        for h in ref + bat:
+            lbm.lbm_destroy(h)
+
+
+def test_batch_d3q27_uneven_boxes():
+    lbm = _lbm()
+    dims = [(24, 20, 18), (40, 12, 30), (13, 33, 9)]
+    hs_ref, hs_bat = [], []
+    for k, d in enumerate(dims):
+        f = I.smooth_random(3, d, seed=60 + k, u_amp=0.05)
+        for lst in (hs_ref, hs_bat):
+            h = lbm.lbm_create(3, d, 1.4, 0.7, 0.02, precision=lbm.LBM_FP32_DEV, visc_exponent=0.76, T_ref=0.15)
+            lbm.lbm_init_fields(h, *f)
+            lst.append(h)
+    b = lbm.lbm_batch_create(hs_bat)
+    try:
+        print("[gpu case] D3Q27 batch", dims, flush=True)
+        lbm.lbm_batch_step(b, 11, 4)
+        for h in hs_ref:
+            lbm.lbm_step(h, 11)
+        assert _same(_states(lbm, hs_ref, True), _states(lbm, hs_bat, True))
+    finally:
+        lbm.lbm_batch_destroy(b)
+        for h in hs_ref + hs_bat:
+            lbm.lbm_destroy(h)
+
+
+def test_batch_argument_errors():
+    lbm = _lbm()
+    h1 = lbm.lbm_create(2, (32, 32), 1.4, 0.7, 0.02, precision=lbm.LBM_FP32_DEV)
+    h2 = lbm.lbm_create(2, (32, 32), 1.4, 0.7, 0.02, precision=lbm.LBM_FP64)
+    try:
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_batch_create([h1, h2])
+        assert e.value.code == lbm.LBM_EINVAL
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_batch_create([h1, h1])
+        assert e.value.code == lbm.LBM_EINVAL
+        b = lbm.lbm_batch_create([h1])
+        try:
+            with pytest.raises(lbm.LbmError) as e:
+                lbm.lbm_batch_step(b, 1)
+            assert e.value.code == lbm.LBM_ESTATE  # no lbm_init_fields yet
+            with pytest.raises(lbm.LbmError) as e:
+                lbm.lbm_batch_set_tile(b, (48, 1, 8))
+            assert e.value.code == lbm.LBM_EINVAL
+        finally:
+            lbm.lbm_batch_destroy(b)
+    finally:
+        lbm.lbm_destroy(h1)
+        lbm.lbm_destroy(h2)

@@ -88,3 +88,45 @@ def test_shock_vortex_states():
     assert np.allclose((p / rho ** g)[~up], rh["p2"] / rh["rho2"] ** g, rtol=1e-12)
     # far from the vortex the base state is recovered
     assert abs(rho[0, 0, 5] - rh["rho1"]) < 1e-6 and abs(rho[0, 0, 250] - rh["rho2"]) < 1e-6
+
+
+@pytest.mark.parametrize("nx,ny", [(64, 96), (160, 64), (128, 128)])
+def test_box2d_turbulence_is_real_solenoidal_and_scaled(nx, ny):
+    rho, u, T = I.turbulence_box2d(nx, ny, seed=3, Ma_t=0.4, T0=0.15)
+    assert u.shape == (2, 1, ny, nx) and rho.shape == (1, ny, nx)
+    ux, uy = u[0, 0], u[1, 0]
+    # spectral divergence of the real field (physical wave numbers per axis)
+    kx = 2 * np.pi * np.fft.fftfreq(nx)
+    ky = 2 * np.pi * np.fft.fftfreq(ny)
+    div = np.fft.ifft2(1j * kx[None, :] * np.fft.fft2(ux) + 1j * ky[:, None] * np.fft.fft2(uy)).real
+    assert np.abs(div).max() < 1e-12 * np.abs(u).max()
+    assert np.sqrt((u ** 2).sum(0).mean()) == pytest.approx(0.4 * np.sqrt(1.4 * 0.15), rel=1e-12)
+    # the energy peaks at the shell k0 = 4 (units of 2 pi / min(nx, ny))
+    L = min(nx, ny)
+    KX, KY = np.meshgrid(np.fft.fftfreq(nx, 1 / nx) / nx, np.fft.fftfreq(ny, 1 / ny) / ny, indexing="xy")
+    shell = np.rint(np.sqrt(KX ** 2 + KY ** 2) * L).astype(int)
+    e = np.bincount(shell.ravel(), (np.abs(np.fft.fft2(ux)) ** 2 + np.abs(np.fft.fft2(uy)) ** 2).ravel())
+    assert 3 <= int(np.argmax(e)) <= 4  # continuous maximum of k^4 exp(-2 k^2/16) is at k = 4
+
+
+def test_taylor_viscosity_matches_closed_form_on_a_cube():
+    """On the 3-D cube generator the measured microscale gives the closed-form
+    mu_0 of turbulence_viscosity (lambda = 2/k0) to within the discreteness of
+    the shells."""
+    n = 64
+    rho, u, T = I.turbulence(3, n, seed=1, Ma_t=0.5, T0=0.15)
+    mu_meas = I.taylor_viscosity(u, Re_lambda=72.0)
+    mu_closed = I.turbulence_viscosity(n, Ma_t=0.5, T0=0.15, Re_lambda=72.0)
+    assert mu_meas == pytest.approx(mu_closed, rel=0.02)
+
+
+def test_ensemble_2d_sizes_and_parameters():
+    boxes = I.ensemble_2d(count=8)
+    assert [b["seed"] for b in boxes] == list(range(8))
+    for b in boxes:
+        nx, ny = b["dims"]
+        assert nx in range(64, 513, 32) and ny in range(64, 513, 32)
+        assert 0.1 <= b["Ma_t"] <= 0.6 and b["mu"] > 0
+        assert b["fields"][1].shape == (2, 1, ny, nx)
+    again = I.ensemble_2d(count=2)
+    assert np.array_equal(again[1]["fields"][1], boxes[1]["fields"][1])
