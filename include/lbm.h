@@ -140,6 +140,20 @@ int lbm_set_state(lbm_handle h, const void* buf, size_t bytes, int mem, int64_t 
 int64_t lbm_step_count(lbm_handle h);
 /* Message of the last failure on this thread ("" if none).  h is unused. */
 const char* lbm_last_error(lbm_handle h);
+/* Adds increments to the macroscopic fields of the stored state: with (rho,
+   u, T) the moments of the stored populations and (rho', u', T') = (rho +
+   drho, u + du, T + dT), f_i += f^eq_i(rho', u', T') - f^eq_i(rho, u, T) and
+   likewise g (Eqs. (20), (42)), so the non-equilibrium parts are kept and the
+   moments become (rho', u', T').  Arrays as in lbm_init_fields; LBM_EINVAL if
+   a new rho or T is not positive (nothing changed then). */
+int lbm_fields_add(lbm_handle h, const double* drho, const double* du, const double* dT, int mem);
+/* Box filter of the stored moments onto the coarse grid of factor^D times
+   fewer nodes (every dim divisible by factor; for D2Q9 the z factor is 1):
+   rho_c = mean rho, (rho u)_c = mean rho u, (rho E)_c = mean rho E, and
+   u_c = (rho u)_c / rho_c, T_c = ((rho E)_c / rho_c - |u_c|^2 / 2) / C_v, so
+   mass, momentum and energy are kept.  Outputs on the coarse grid (node
+   order as for the fields). */
+int lbm_filter_moments(lbm_handle h, int factor, double* rho, double* u, double* T, int mem);
 /* Plain device-to-device copy of bytes (multiple of 16) on hip_stream, by the
    library's own vectorised copy kernel: the reference for achievable HBM
    bandwidth and for scaling hardware byte counters. */

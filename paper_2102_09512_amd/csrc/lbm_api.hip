@@ -34,6 +34,12 @@ int hip_fail(hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
 
+}  // namespace
+
+int lbm::set_error(int code, const std::string& msg) { return fail(code, msg); }
+
+namespace {
+
 size_t word_of(int precision) { return precision == LBM_FP64 ? sizeof(double) : sizeof(float); }
 
 int select_device(Ctx* c) {
@@ -245,6 +251,7 @@ int lbm_destroy(lbm_handle h) {
   for (int k = 0; k < 2; ++k)
     if (c->buf[k]) hipFree(c->buf[k]);
   if (c->fields) hipFree(c->fields);
+  if (c->work) hipFree(c->work);
   if (c->partial) hipFree(c->partial);
   if (c->diag_dev) hipFree(c->diag_dev);
   delete c;
@@ -409,6 +416,71 @@ int lbm_set_state(lbm_handle h, const void* buf, size_t bytes, int mem, int64_t 
 }
 
 int64_t lbm_step_count(lbm_handle h) { return h ? h->step : -1; }
+
+int lbm_fields_add(lbm_handle h, const double* drho, const double* du, const double* dT, int mem) {
+  if (!h) return fail(LBM_EINVAL, "lbm_fields_add: NULL handle");
+  if (!drho || !du || !dT) return fail(LBM_EINVAL, "lbm_fields_add: NULL increment");
+  if (mem != LBM_HOST && mem != LBM_DEVICE) return fail(LBM_EINVAL, "lbm_fields_add: bad memory kind");
+  Ctx* c = h;
+  if (!c->initialised) return fail(LBM_ESTATE, "lbm_fields_add: no state (lbm_init_fields)");
+  int rc = select_device(c);
+  if (rc) return rc;
+  if ((rc = ensure_scratch(c))) return rc;
+  const int64_t N = c->N;
+  const int D = c->lattice;
+  if (!c->work) HIP_OR_FAIL(hipMalloc(&c->work, sizeof(double) * 10 * (size_t)N), "hipMalloc(work)");
+  double* newf = c->work;
+  if (mem == LBM_HOST) {
+    double* st = c->work + 5 * N;
+    HIP_OR_FAIL(hipMemcpyAsync(st, drho, sizeof(double) * N, hipMemcpyHostToDevice, c->stream), "copy drho");
+    HIP_OR_FAIL(hipMemcpyAsync(st + N, du, sizeof(double) * N * D, hipMemcpyHostToDevice, c->stream), "copy du");
+    HIP_OR_FAIL(hipMemcpyAsync(st + 4 * N, dT, sizeof(double) * N, hipMemcpyHostToDevice, c->stream), "copy dT");
+    drho = st;
+    du = st + N;
+    dT = st + 4 * N;
+  }
+  HIP_OR_FAIL(lbm::launch_fields(*c, c->buf[c->cur], c->fields), "moments kernel");
+  HIP_OR_FAIL(lbm::launch_fields_plus(*c, c->fields, drho, du, dT, newf), "increment kernel");
+  HIP_OR_FAIL(lbm::launch_validate(*c, newf, newf + N, newf + 4 * N, c->partial, c->partial_blocks, c->diag_dev),
+              "validate");
+  double bad = 0.0;
+  HIP_OR_FAIL(hipMemcpyAsync(&bad, c->diag_dev, sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy count");
+  HIP_OR_FAIL(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  if (bad != 0.0) return fail(LBM_EINVAL, "lbm_fields_add: non-finite value or rho <= 0 or T <= 0 after the increment");
+  HIP_OR_FAIL(lbm::launch_fields_add(*c, c->buf[c->cur], c->fields, newf), "re-equilibration kernel");
+  return LBM_OK;
+}
+
+int lbm_filter_moments(lbm_handle h, int factor, double* rho, double* u, double* T, int mem) {
+  if (!h) return fail(LBM_EINVAL, "lbm_filter_moments: NULL handle");
+  if (!rho || !u || !T) return fail(LBM_EINVAL, "lbm_filter_moments: NULL output");
+  if (mem != LBM_HOST && mem != LBM_DEVICE) return fail(LBM_EINVAL, "lbm_filter_moments: bad memory kind");
+  Ctx* c = h;
+  if (!c->initialised) return fail(LBM_ESTATE, "lbm_filter_moments: no state (lbm_init_fields)");
+  const int D = c->lattice;
+  if (factor < 1 || c->n[0] % factor || c->n[1] % factor || (D == 3 && c->n[2] % factor))
+    return fail(LBM_EINVAL, "lbm_filter_moments: dims not divisible by the factor");
+  int rc = select_device(c);
+  if (rc) return rc;
+  if ((rc = ensure_scratch(c))) return rc;
+  const int64_t Nc = (c->n[0] / factor) * (c->n[1] / factor) * (D == 3 ? c->n[2] / factor : 1);
+  double *r = rho, *v = u, *t = T;
+  if (mem == LBM_HOST) {
+    if (!c->work) HIP_OR_FAIL(hipMalloc(&c->work, sizeof(double) * 10 * (size_t)c->N), "hipMalloc(work)");
+    r = c->work;
+    v = r + Nc;
+    t = v + 3 * Nc;
+  }
+  HIP_OR_FAIL(lbm::launch_fields(*c, c->buf[c->cur], c->fields), "moments kernel");
+  HIP_OR_FAIL(lbm::launch_filter(*c, c->fields, factor, r, v, t), "filter kernel");
+  if (mem == LBM_HOST) {
+    HIP_OR_FAIL(hipMemcpyAsync(rho, r, sizeof(double) * Nc, hipMemcpyDeviceToHost, c->stream), "copy rho");
+    HIP_OR_FAIL(hipMemcpyAsync(u, v, sizeof(double) * Nc * D, hipMemcpyDeviceToHost, c->stream), "copy u");
+    HIP_OR_FAIL(hipMemcpyAsync(T, t, sizeof(double) * Nc, hipMemcpyDeviceToHost, c->stream), "copy T");
+    HIP_OR_FAIL(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  }
+  return LBM_OK;
+}
 
 int lbm_device_copy(void* dst, const void* src, size_t bytes, void* stream) {
   if (!dst || !src) return fail(LBM_EINVAL, "lbm_device_copy: NULL pointer");

@@ -57,6 +57,7 @@ struct Ctx {
   void* buf[2] = {nullptr, nullptr}; // population buffers (2Q x ps elements each)
   int cur = 0;                       // buffer holding the current state
   double* fields = nullptr;          // 6 x N doubles: rho, ux, uy, uz, T, rhoE
+  double* work = nullptr;            // 10 x N doubles, on first use: new fields and staged increments
   double* partial = nullptr;         // per-block partial sums
   double* diag_dev = nullptr;        // final sums
   int partial_blocks = 0;
@@ -104,6 +105,12 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 // Internal population layout <-> the ABI state layout (2Q arrays of N values).
 hipError_t launch_pack(const Ctx& c, const void* pops, void* state);
 hipError_t launch_unpack(const Ctx& c, const void* state, void* pops);
+// Records msg as the calling thread's last error (lbm_last_error); returns code.
+int set_error(int code, const std::string& msg);
+hipError_t launch_fields_add(const Ctx& c, void* pops, const double* oldf, const double* newf);
+hipError_t launch_fields_plus(const Ctx& c, const double* oldf, const double* drho, const double* du, const double* dT,
+                              double* newf);
+hipError_t launch_filter(const Ctx& c, const double* fields, int factor, double* rho, double* u, double* T);
 hipError_t launch_batch_step(const Batch& b, hipStream_t s, int flip);
 hipError_t launch_toggle(const Batch& b, hipStream_t s);
 // Default launch tile for a lattice/precision and whether a tile is available.

@@ -788,6 +788,128 @@ hipError_t launch_init(const Ctx& c, const double* rho, const double* u, const d
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Field increments by re-equilibration, and the conservative box filter
+// ---------------------------------------------------------------------------
+
+// f_i += f^eq_i(new) - f^eq_i(old), g likewise (equilibria evaluated in FP64
+// for either storage).  oldf, newf: rho, ux, uy, uz, T planes (N each).
+template <int D, bool DEV, typename S>
+__global__ void __launch_bounds__(256) fields_add_kernel(S* __restrict__ pops, const double* __restrict__ oldf,
+                                                         const double* __restrict__ newf, long long N,
+                                                         const StepParams p) {
+  constexpr int Q = lat_q(D);
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const NodeConsts k = node_consts(p);
+  double fo[Q], go[Q], fn[Q], gn[Q];
+  const double d0[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int w = 0; w < 2; ++w) {
+    const double* F = w ? newf : oldf;
+    NodeMoments<double> m;
+    m.rho = F[n];
+    m.drho = F[n] - p.rho0;
+    m.T = F[4 * N + n];
+    m.dT = F[4 * N + n] - p.T0;
+    for (int a = 0; a < 3; ++a) {
+      const double ua = a < D ? F[(1 + a) * N + n] : 0.0;
+      m.u[a] = ua;
+      m.du[a] = ua - p.u0[a];
+    }
+    m.omega = m.omega1 = 1.0;
+    m.corr = 0.0;
+    if (w) equilibria<D, double, DEV>(m, d0, k, fn, gn);
+    else equilibria<D, double, DEV>(m, d0, k, fo, go);
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    S& fi = pops[pop_offset(p, Q, i, n)];
+    S& gi = pops[pop_offset(p, Q, i + Q, n)];
+    fi = (S)((double)fi + (fn[i] - fo[i]));
+    gi = (S)((double)gi + (gn[i] - go[i]));
+  }
+}
+
+// new = old + increments (rho, u planes, T); increments d: drho[N], du[D N], dT[N]
+__global__ void __launch_bounds__(256) fields_plus_kernel(const double* __restrict__ oldf, const double* __restrict__ drho,
+                                                          const double* __restrict__ du, const double* __restrict__ dT,
+                                                          double* __restrict__ newf, long long N, int D) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  newf[n] = oldf[n] + drho[n];
+  for (int a = 0; a < 3; ++a) newf[(1 + a) * N + n] = oldf[(1 + a) * N + n] + (a < D ? du[a * N + n] : 0.0);
+  newf[4 * N + n] = oldf[4 * N + n] + dT[n];
+}
+
+// coarse node: means of rho, rho u and rho E over its factor^D fine nodes
+__global__ void __launch_bounds__(256) filter_kernel(const double* __restrict__ fields, long long N, int nx, int ny,
+                                                     int nz, int f, int fz, int D, double Cv, double* __restrict__ rho,
+                                                     double* __restrict__ u, double* __restrict__ T) {
+  const int cx = nx / f, cy = ny / f, cz = nz / fz;
+  const long long Nc = (long long)cx * cy * cz;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Nc) return;
+  const int X = (int)(c % cx), Y = (int)((c / cx) % cy), Z = (int)(c / ((long long)cx * cy));
+  double sr = 0.0, sj[3] = {0.0, 0.0, 0.0}, se = 0.0;
+  for (int k = 0; k < fz; ++k)
+    for (int j = 0; j < f; ++j)
+      for (int i = 0; i < f; ++i) {
+        const long long n = (long long)(X * f + i) + nx * ((long long)(Y * f + j) + (long long)ny * (Z * fz + k));
+        const double r = fields[n];
+        sr += r;
+        for (int a = 0; a < 3; ++a) sj[a] += r * fields[(1 + a) * N + n];
+        se += fields[5 * N + n];
+      }
+  const double inv = 1.0 / sr;
+  double u2 = 0.0;
+  for (int a = 0; a < D; ++a) {
+    const double ua = sj[a] * inv;
+    u[a * Nc + c] = ua;
+    u2 += ua * ua;
+  }
+  const double cnt = (double)f * f * fz;
+  rho[c] = sr / cnt;
+  T[c] = (se * inv - 0.5 * u2) / Cv;
+}
+
+hipError_t launch_fields_add(const Ctx& c, void* pops, const double* oldf, const double* newf) {
+  const long long N = c.N;
+  const dim3 grid((unsigned)((N + 255) / 256)), block(256);
+  if (c.lattice == 3) {
+    if (c.precision == LBM_FP64)
+      hipLaunchKernelGGL((fields_add_kernel<3, false, double>), grid, block, 0, c.stream, (double*)pops, oldf, newf, N,
+                         c.sp);
+    else
+      hipLaunchKernelGGL((fields_add_kernel<3, true, float>), grid, block, 0, c.stream, (float*)pops, oldf, newf, N,
+                         c.sp);
+  } else {
+    if (c.precision == LBM_FP64)
+      hipLaunchKernelGGL((fields_add_kernel<2, false, double>), grid, block, 0, c.stream, (double*)pops, oldf, newf, N,
+                         c.sp);
+    else
+      hipLaunchKernelGGL((fields_add_kernel<2, true, float>), grid, block, 0, c.stream, (float*)pops, oldf, newf, N,
+                         c.sp);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fields_plus(const Ctx& c, const double* oldf, const double* drho, const double* du, const double* dT,
+                              double* newf) {
+  const long long N = c.N;
+  hipLaunchKernelGGL(fields_plus_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, c.stream, oldf, drho, du, dT,
+                     newf, N, c.lattice);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter(const Ctx& c, const double* fields, int factor, double* rho, double* u, double* T) {
+  const int fz = c.lattice == 3 ? factor : 1;
+  const long long Nc = (c.n[0] / factor) * (c.n[1] / factor) * (c.n[2] / fz);
+  hipLaunchKernelGGL(filter_kernel, dim3((unsigned)((Nc + 255) / 256)), dim3(256), 0, c.stream, fields, c.N,
+                     (int)c.n[0], (int)c.n[1], (int)c.n[2], factor, fz, c.lattice, c.sp.Cv, rho, u, T);
+  return hipGetLastError();
+}
+
 hipError_t launch_fields(const Ctx& c, const void* pops, double* fields) {
   const long long N = c.N;
   const dim3 grid((unsigned)((N + 255) / 256)), block(256);

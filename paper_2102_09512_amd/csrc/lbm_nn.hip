@@ -1,0 +1,625 @@
+// Learned coarse-grid corrector of liblbm.so: 3x3x3 periodic convolutions
+// on bf16 matrix cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation),
+// forward, backward-data and backward-weight kernels, the training loss and
+// an FP32 Adam step.  The C ABI is in lbm_nn.h.
+//
+// Layouts.  Activations are bf16, channels-last: a[v][C] with v the node
+// index (x fastest) and C = 16 (the network input, zero-padded) or 32 (every
+// layer output, zero-padded past the layer's width).  Weights are kept in
+// FP32 as W[t][i][o] (tap t = (dx+1) + 3(dy+1) + 9(dz+1)) and packed to bf16
+// for the matrix cores as wp[t][i/16][o][i%16] (forward) and, for the
+// gradient with respect to the layer input, as the convolution with the
+// mirrored taps and exchanged channels, wb[t][o/16][i][o%16].
+//
+// Matrix-core tiles.  One wavefront computes 32 nodes x 32 output channels:
+// lane l supplies A[m = l%32][k = 8(l/32) .. +7] (node m, 8 input channels)
+// and B[k][n = l%32] (8 input channels of output channel n); accumulator i
+// of lane l holds the result for node 8(i/4) + 4(l/32) + i%4 and output
+// channel l%32.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm_internal.h"
+#include "lbm_nn.h"
+
+namespace lbmnn {
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+struct Grid {
+  int nx, ny, nz;
+};
+
+__device__ inline int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// node v moved by tap t, periodic
+__device__ inline int shifted(int v, int t, const Grid g) {
+  const int x = v % g.nx, y = (v / g.nx) % g.ny, z = v / (g.nx * g.ny);
+  return wrap(x + t % 3 - 1, g.nx) + g.nx * (wrap(y + (t / 3) % 3 - 1, g.ny) + g.ny * wrap(z + t / 9 - 1, g.nz));
+}
+
+// planar FP32 x[c][v] (c < cin) -> bf16 a[v][16], (x - mean) / std, zero padded
+__global__ void __launch_bounds__(256) pack_input_kernel(const float* __restrict__ x, int cin, const float* __restrict__ mean,
+                                                         const float* __restrict__ inv_std, __bf16* __restrict__ a, int V) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  bf8 lo, hi;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    lo[c] = (__bf16)(c < cin ? (x[(size_t)c * V + v] - mean[c]) * inv_std[c] : 0.f);
+    hi[c] = (__bf16)(c + 8 < cin ? (x[(size_t)(c + 8) * V + v] - mean[c + 8]) * inv_std[c + 8] : 0.f);
+  }
+  *(bf8*)(a + (size_t)v * 16) = lo;
+  *(bf8*)(a + (size_t)v * 16 + 8) = hi;
+}
+
+// out[v][o] = bias[o] + sum_t sum_i in[shift(v, t)][i] w[t][i][o]  (cross-correlation)
+// CIN: channels of in (16 or 32).  OUT_PLANAR: write FP32 planes out[o][v] for
+// o < cout, else bf16 out[v][32].  relu: max(., 0).  mask (bf16 [v][32], may
+// be null): zero where mask <= 0 (the derivative of the ReLU that produced it).
+template <int CIN, bool OUT_PLANAR>
+__global__ void __launch_bounds__(256) conv_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ wp,
+                                                   const float* __restrict__ bias, int relu,
+                                                   const __bf16* __restrict__ mask, void* __restrict__ out, int cout,
+                                                   const Grid g, int V) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int v0 = (blockIdx.x * 4 + wave) * 32;
+  if (v0 >= V) return;
+  const int r = lane & 31, half = lane >> 5;
+  const int vm = v0 + r;
+  f16v acc = {};
+#pragma unroll 1
+  for (int t = 0; t < 27; ++t) {
+    const __bf16* src = in + (size_t)shifted(vm, t, g) * CIN + 8 * half;
+    const __bf16* wt = wp + ((size_t)t * (CIN / 16) * 32 + r) * 16 + 8 * half;
+#pragma unroll
+    for (int cc = 0; cc < CIN / 16; ++cc) {
+      const bf8 a = *(const bf8*)(src + cc * 16);
+      const bf8 b = *(const bf8*)(wt + (size_t)cc * 32 * 16);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+  }
+  const float bo = bias ? bias[r] : 0.f;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int v = v0 + 8 * (i >> 2) + 4 * half + (i & 3);
+    float y = acc[i] + bo;
+    if (relu) y = y > 0.f ? y : 0.f;
+    if (mask && !((float)mask[(size_t)v * 32 + r] > 0.f)) y = 0.f;
+    if (OUT_PLANAR) {
+      if (r < cout) static_cast<float*>(out)[(size_t)r * V + v] = y;
+    } else {
+      static_cast<__bf16*>(out)[(size_t)v * 32 + r] = (__bf16)y;
+    }
+  }
+}
+
+// Partial weight gradients: part[task][i][o] = sum over the chunk's nodes v of
+// in[shift(v, t)][i] dout[v][o], task = t * nchunks + chunk (rows i >= CIN zero).
+template <int CIN>
+__global__ void __launch_bounds__(256) wgrad_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ dout,
+                                                    float* __restrict__ part, const Grid g, int V, int chunk) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nchunks = V / chunk;
+  const int task = blockIdx.x * 4 + wave;
+  if (task >= 27 * nchunks) return;
+  const int t = task / nchunks, ch = task % nchunks;
+  const int r = lane & 31, half = lane >> 5;
+  f16v acc = {};
+#pragma unroll 1
+  for (int vb = ch * chunk; vb < (ch + 1) * chunk; vb += 16) {
+    bf8 a, b;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int v = vb + 8 * half + j;
+      a[j] = r < CIN ? in[(size_t)shifted(v, t, g) * CIN + r] : (__bf16)0.f;  // A[i = r][k = v]
+      b[j] = dout[(size_t)v * 32 + r];                                      // B[k = v][o = r]
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+  }
+  float* dst = part + (size_t)task * 1024;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) dst[(8 * (i >> 2) + 4 * half + (i & 3)) * 32 + r] = acc[i];
+}
+
+// grad[t][i][o] += sum_chunk part[t * nchunks + chunk][i][o] for i < cin, o < cout
+__global__ void __launch_bounds__(256) wgrad_reduce_kernel(const float* __restrict__ part, int nchunks, int cin, int cout,
+                                                           float* __restrict__ grad) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 27 * cin * cout) return;
+  const int o = e % cout, i = (e / cout) % cin, t = e / (cout * cin);
+  float s = 0.f;
+  for (int c = 0; c < nchunks; ++c) s += part[((size_t)t * nchunks + c) * 1024 + i * 32 + o];
+  grad[e] += s;
+}
+
+// grad_b[o] += sum_v dout[v][o]: one block per output channel
+__global__ void __launch_bounds__(256) bgrad_kernel(const __bf16* __restrict__ dout, int V, float* __restrict__ grad_b) {
+  __shared__ float red[256];
+  const int o = blockIdx.x;
+  float s = 0.f;
+  for (int v = threadIdx.x; v < V; v += blockDim.x) s += (float)dout[(size_t)v * 32 + o];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grad_b[o] += red[0];
+}
+
+// r = y + (x - target) / std; loss partial sums of r^2; dout[v][c] = 2 r / (C V)
+__global__ void __launch_bounds__(256) loss_kernel(const float* __restrict__ y, const float* __restrict__ x,
+                                                   const float* __restrict__ tgt, const float* __restrict__ inv_std,
+                                                   int C, int V, __bf16* __restrict__ dout, double* __restrict__ partial) {
+  __shared__ double red[256];
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (v < V) {
+    const float scale = 2.f / ((float)C * (float)V);
+#pragma unroll 1
+    for (int c = 0; c < 32; ++c) {
+      float g = 0.f;
+      if (c < C) {
+        const float rr = y[(size_t)c * V + v] + (x[(size_t)c * V + v] - tgt[(size_t)c * V + v]) * inv_std[c];
+        s += (double)rr * rr;
+        g = scale * rr;
+      }
+      dout[(size_t)v * 32 + c] = (__bf16)g;
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ p, const float* __restrict__ g,
+                                                   float* __restrict__ m, float* __restrict__ v, long long n, float lr,
+                                                   float b1, float b2, float eps, float gscale, float c1, float c2) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i] * gscale;
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+// bf16 copies of one layer's FP32 weights W[t][i][o] (cin x cout):
+// wp[t][i/16][o][i%16] (CINP padded inputs, 32 outputs) and
+// wb[t][o/16][i][o%16] = W[26 - t][i][o] (32 padded outputs as inputs, 32 rows)
+__global__ void __launch_bounds__(256) pack_weights_kernel(const float* __restrict__ W, int cin, int cout, int cinp,
+                                                           __bf16* __restrict__ wp, __bf16* __restrict__ wb) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < 27 * cinp * 32) {  // wp element (t, cc, o, k)
+    const int k = e % 16, o = (e / 16) % 32, cc = (e / 512) % (cinp / 16), t = e / (512 * (cinp / 16));
+    const int i = cc * 16 + k;
+    wp[e] = (__bf16)(i < cin && o < cout ? W[((size_t)t * cin + i) * cout + o] : 0.f);
+  }
+  if (wb && e < 27 * 32 * 32) {  // wb element (t, oc, i, k): input channel of the mirrored conv = o
+    const int k = e % 16, i = (e / 16) % 32, oc = (e / 512) % 2, t = e / 1024;
+    const int o = oc * 16 + k;
+    wb[e] = (__bf16)(i < cin && o < cout ? W[((size_t)(26 - t) * cin + i) * cout + o] : 0.f);
+  }
+}
+
+// FP64 fields of a lattice Boltzmann handle (rho, u planes, T) -> FP32 planes
+__global__ void __launch_bounds__(256) fields_to_input_kernel(const double* __restrict__ rho, const double* __restrict__ u,
+                                                              const double* __restrict__ T, int D, int V,
+                                                              float* __restrict__ x) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  x[v] = (float)rho[v];
+  for (int a = 0; a < D; ++a) x[(size_t)(1 + a) * V + v] = (float)u[(size_t)a * V + v];
+  x[(size_t)(1 + D) * V + v] = (float)T[v];
+}
+
+// normalised correction planes -> FP64 increments drho[V], du[D V], dT[V]
+__global__ void __launch_bounds__(256) output_to_increments_kernel(const float* __restrict__ y,
+                                                                   const float* __restrict__ sd, int D, int V,
+                                                                   double* __restrict__ drho, double* __restrict__ du,
+                                                                   double* __restrict__ dT) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  drho[v] = (double)y[v] * sd[0];
+  for (int a = 0; a < D; ++a) du[(size_t)a * V + v] = (double)y[(size_t)(1 + a) * V + v] * sd[1 + a];
+  dT[v] = (double)y[(size_t)(1 + D) * V + v] * sd[1 + D];
+}
+
+}  // namespace lbmnn
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+namespace {
+
+int nn_fail(int code, const std::string& msg) { return lbm::set_error(code, msg); }
+
+int nn_hip(hipError_t e, const char* what) {
+  return nn_fail(LBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define NN_HIP(expr, what)                            \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return nn_hip(e_, what);    \
+  } while (0)
+
+struct Layer {
+  int cin, cout, cinp;          // channels, padded input channels (16 or 32)
+  long long w_off, b_off;       // offsets in the parameter vector
+  __bf16 *wp = nullptr, *wb = nullptr;
+};
+
+}  // namespace
+
+struct lbm_nn_ctx {
+  int L = 0;
+  std::vector<int> ch;
+  lbmnn::Grid g{};
+  int V = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::vector<Layer> layers;
+  long long nparam = 0;
+  float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
+  float *mean = nullptr, *inv_std = nullptr, *std_dev = nullptr;  // device, 16 each
+  std::vector<double> std_host;
+  std::vector<__bf16*> act;     // act[l]: input of layer l (bf16 [V][16 or 32]); act[L] unused
+  __bf16 *dA = nullptr, *dB = nullptr;  // gradient ping-pong, bf16 [V][32]
+  float* y = nullptr;                   // network output planes [c_L][V]
+  float* part = nullptr;                // weight-gradient partials
+  int chunk = 256;
+  double* lpart = nullptr;              // loss partials
+  float* fld = nullptr;                 // corrector staging: fields and correction (FP32)
+  double* dfld = nullptr;               // FP64 fields / increments for lbm
+};
+
+namespace {
+
+int nn_select(lbm_nn n) {
+  int cur = -1;
+  NN_HIP(hipGetDevice(&cur), "hipGetDevice");
+  if (cur != n->device) NN_HIP(hipSetDevice(n->device), "hipSetDevice");
+  return LBM_OK;
+}
+
+int nn_pack_weights(lbm_nn n) {
+  for (int l = 0; l < n->L; ++l) {
+    Layer& ly = n->layers[l];
+    const int total = 27 * 32 * 32 > 27 * ly.cinp * 32 ? 27 * 32 * 32 : 27 * ly.cinp * 32;
+    hipLaunchKernelGGL(lbmnn::pack_weights_kernel, dim3((total + 255) / 256), dim3(256), 0, n->stream,
+                       n->params + ly.w_off, ly.cin, ly.cout, ly.cinp, ly.wp, l > 0 ? ly.wb : nullptr);
+    NN_HIP(hipGetLastError(), "pack weights");
+  }
+  return LBM_OK;
+}
+
+template <int CIN, bool PLANAR>
+hipError_t conv(lbm_nn n, const __bf16* in, const __bf16* w, const float* bias, int relu, const __bf16* mask,
+                void* out, int cout) {
+  const int blocks = (n->V / 32 + 3) / 4;
+  hipLaunchKernelGGL((lbmnn::conv_kernel<CIN, PLANAR>), dim3(blocks), dim3(256), 0, n->stream, in, w, bias, relu,
+                     mask, out, cout, n->g, n->V);
+  return hipGetLastError();
+}
+
+// forward pass of normalised x into n->y; activations kept for the backward pass
+int nn_forward(lbm_nn n, const float* x) {
+  hipLaunchKernelGGL(lbmnn::pack_input_kernel, dim3((n->V + 255) / 256), dim3(256), 0, n->stream, x, n->ch[0],
+                     n->mean, n->inv_std, n->act[0], n->V);
+  NN_HIP(hipGetLastError(), "pack input");
+  for (int l = 0; l < n->L; ++l) {
+    const Layer& ly = n->layers[l];
+    const bool last = l == n->L - 1;
+    const float* b = n->params + ly.b_off;
+    hipError_t e;
+    if (ly.cinp == 16)
+      e = last ? conv<16, true>(n, n->act[l], ly.wp, b, 0, nullptr, n->y, ly.cout)
+               : conv<16, false>(n, n->act[l], ly.wp, b, 1, nullptr, n->act[l + 1], ly.cout);
+    else
+      e = last ? conv<32, true>(n, n->act[l], ly.wp, b, 0, nullptr, n->y, ly.cout)
+               : conv<32, false>(n, n->act[l], ly.wp, b, 1, nullptr, n->act[l + 1], ly.cout);
+    NN_HIP(e, "conv forward");
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_nn_create(lbm_nn* out, int layers, const int* channels, const int64_t dims[3]) {
+  if (!out) return nn_fail(LBM_EINVAL, "lbm_nn_create: out is NULL");
+  *out = nullptr;
+  if (layers < 1 || !channels || !dims) return nn_fail(LBM_EINVAL, "lbm_nn_create: bad layer description");
+  if (channels[0] < 1 || channels[0] > 16) return nn_fail(LBM_EINVAL, "lbm_nn_create: input channels must be 1..16");
+  for (int l = 1; l < layers; ++l)
+    if (channels[l] != 32) return nn_fail(LBM_EINVAL, "lbm_nn_create: hidden widths must be 32");
+  if (channels[layers] < 1 || channels[layers] > 32)
+    return nn_fail(LBM_EINVAL, "lbm_nn_create: output channels must be 1..32");
+  for (int a = 0; a < 3; ++a)
+    if (dims[a] < 1 || dims[a] > 4096) return nn_fail(LBM_EINVAL, "lbm_nn_create: dims out of range");
+  const int64_t V = dims[0] * dims[1] * dims[2];
+  if (V % 256 || V > (1 << 26)) return nn_fail(LBM_EINVAL, "lbm_nn_create: node count must be a multiple of 256 (<= 2^26)");
+  lbm_nn n = new (std::nothrow) lbm_nn_ctx();
+  if (!n) return nn_fail(LBM_ENOMEM, "lbm_nn_create: host allocation failed");
+  n->L = layers;
+  n->ch.assign(channels, channels + layers + 1);
+  n->g = {(int)dims[0], (int)dims[1], (int)dims[2]};
+  n->V = (int)V;
+  long long off = 0;
+  for (int l = 0; l < layers; ++l) {
+    Layer ly;
+    ly.cin = channels[l];
+    ly.cout = channels[l + 1];
+    ly.cinp = l == 0 ? 16 : 32;
+    ly.w_off = off;
+    off += 27LL * ly.cin * ly.cout;
+    ly.b_off = off;
+    off += ly.cout;
+    n->layers.push_back(ly);
+  }
+  n->nparam = off;
+  n->std_host.assign(16, 1.0);
+  int rc = LBM_OK;
+  auto alloc = [&](void** p, size_t bytes) {
+    if (rc != LBM_OK) return;
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) rc = nn_hip(e, "lbm_nn_create: hipMalloc");
+  };
+  hipError_t e0 = hipGetDevice(&n->device);
+  if (e0 != hipSuccess) rc = nn_hip(e0, "hipGetDevice");
+  const size_t P = sizeof(float) * (size_t)off;
+  alloc((void**)&n->params, P);
+  alloc((void**)&n->grads, P);
+  alloc((void**)&n->m, P);
+  alloc((void**)&n->v, P);
+  alloc((void**)&n->mean, 16 * sizeof(float));
+  alloc((void**)&n->inv_std, 16 * sizeof(float));
+  alloc((void**)&n->std_dev, 16 * sizeof(float));
+  n->act.assign(layers, nullptr);
+  for (int l = 0; l < layers; ++l) alloc((void**)&n->act[l], sizeof(__bf16) * (size_t)V * (l == 0 ? 16 : 32));
+  alloc((void**)&n->dA, sizeof(__bf16) * (size_t)V * 32);
+  alloc((void**)&n->dB, sizeof(__bf16) * (size_t)V * 32);
+  alloc((void**)&n->y, sizeof(float) * (size_t)V * 32);
+  n->chunk = 256;
+  alloc((void**)&n->part, sizeof(float) * 27 * (size_t)(V / n->chunk) * 1024);
+  alloc((void**)&n->lpart, sizeof(double) * (size_t)((V + 255) / 256));
+  alloc((void**)&n->fld, sizeof(float) * 2 * 16 * (size_t)V);
+  alloc((void**)&n->dfld, sizeof(double) * 10 * (size_t)V);
+  for (Layer& ly : n->layers) {
+    alloc((void**)&ly.wp, sizeof(__bf16) * 27 * ly.cinp * 32);
+    alloc((void**)&ly.wb, sizeof(__bf16) * 27 * 32 * 32);
+  }
+  if (rc == LBM_OK) {
+    std::vector<float> mean(16, 0.f), one(16, 1.f);
+    hipError_t e = hipMemset(n->params, 0, P);
+    if (e == hipSuccess) e = hipMemset(n->grads, 0, P);
+    if (e == hipSuccess) e = hipMemset(n->m, 0, P);
+    if (e == hipSuccess) e = hipMemset(n->v, 0, P);
+    if (e == hipSuccess) e = hipMemcpy(n->mean, mean.data(), 16 * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(n->inv_std, one.data(), 16 * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(n->std_dev, one.data(), 16 * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) rc = nn_hip(e, "lbm_nn_create: initialise");
+  }
+  if (rc == LBM_OK) rc = nn_pack_weights(n);
+  if (rc == LBM_OK) {
+    const hipError_t e = hipStreamSynchronize(n->stream);
+    if (e != hipSuccess) rc = nn_hip(e, "hipStreamSynchronize");
+  }
+  if (rc != LBM_OK) {
+    lbm_nn_destroy(n);
+    return rc;
+  }
+  *out = n;
+  return LBM_OK;
+}
+
+int lbm_nn_destroy(lbm_nn n) {
+  if (!n) return LBM_OK;
+  (void)nn_select(n);
+  if (n->stream) (void)hipStreamSynchronize(n->stream);
+  for (void* p : {(void*)n->params, (void*)n->grads, (void*)n->m, (void*)n->v, (void*)n->mean, (void*)n->inv_std,
+                  (void*)n->std_dev, (void*)n->dA, (void*)n->dB, (void*)n->y, (void*)n->part, (void*)n->lpart,
+                  (void*)n->fld, (void*)n->dfld})
+    if (p) (void)hipFree(p);
+  for (__bf16* p : n->act)
+    if (p) (void)hipFree(p);
+  for (Layer& ly : n->layers) {
+    if (ly.wp) (void)hipFree(ly.wp);
+    if (ly.wb) (void)hipFree(ly.wb);
+  }
+  delete n;
+  return LBM_OK;
+}
+
+int lbm_nn_set_stream(lbm_nn n, void* s) {
+  if (!n) return nn_fail(LBM_EINVAL, "lbm_nn_set_stream: NULL network");
+  n->stream = static_cast<hipStream_t>(s);
+  return LBM_OK;
+}
+
+int64_t lbm_nn_param_count(lbm_nn n) { return n ? n->nparam : -1; }
+
+int lbm_nn_set_params(lbm_nn n, const float* params, int mem) {
+  if (!n || !params) return nn_fail(LBM_EINVAL, "lbm_nn_set_params: NULL argument");
+  if (mem != LBM_HOST && mem != LBM_DEVICE) return nn_fail(LBM_EINVAL, "lbm_nn_set_params: bad memory kind");
+  int rc = nn_select(n);
+  if (rc) return rc;
+  NN_HIP(hipMemcpyAsync(n->params, params, sizeof(float) * n->nparam,
+                        mem == LBM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, n->stream),
+         "copy params");
+  if ((rc = nn_pack_weights(n))) return rc;
+  NN_HIP(hipStreamSynchronize(n->stream), "hipStreamSynchronize");
+  return LBM_OK;
+}
+
+static int nn_copy_out(lbm_nn n, float* dst, const float* src, int mem, const char* what) {
+  if (!n || !dst) return nn_fail(LBM_EINVAL, std::string(what) + ": NULL argument");
+  if (mem != LBM_HOST && mem != LBM_DEVICE) return nn_fail(LBM_EINVAL, std::string(what) + ": bad memory kind");
+  int rc = nn_select(n);
+  if (rc) return rc;
+  NN_HIP(hipMemcpyAsync(dst, src, sizeof(float) * n->nparam,
+                        mem == LBM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, n->stream),
+         what);
+  NN_HIP(hipStreamSynchronize(n->stream), "hipStreamSynchronize");
+  return LBM_OK;
+}
+
+int lbm_nn_get_params(lbm_nn n, float* p, int mem) { return nn_copy_out(n, p, n ? n->params : nullptr, mem, "lbm_nn_get_params"); }
+int lbm_nn_get_grads(lbm_nn n, float* g, int mem) { return nn_copy_out(n, g, n ? n->grads : nullptr, mem, "lbm_nn_get_grads"); }
+
+int lbm_nn_zero_grad(lbm_nn n) {
+  if (!n) return nn_fail(LBM_EINVAL, "lbm_nn_zero_grad: NULL network");
+  int rc = nn_select(n);
+  if (rc) return rc;
+  NN_HIP(hipMemsetAsync(n->grads, 0, sizeof(float) * n->nparam, n->stream), "zero grads");
+  return LBM_OK;
+}
+
+int lbm_nn_set_scaling(lbm_nn n, const double* mean, const double* sd) {
+  if (!n || !mean || !sd) return nn_fail(LBM_EINVAL, "lbm_nn_set_scaling: NULL argument");
+  std::vector<float> m(16, 0.f), is(16, 1.f), s(16, 1.f);
+  for (int c = 0; c < n->ch[0]; ++c) {
+    if (!(sd[c] > 0.0) || !std::isfinite(sd[c]) || !std::isfinite(mean[c]))
+      return nn_fail(LBM_EINVAL, "lbm_nn_set_scaling: std must be finite and > 0");
+    m[c] = (float)mean[c];
+    s[c] = (float)sd[c];
+    is[c] = (float)(1.0 / sd[c]);
+    n->std_host[c] = sd[c];
+  }
+  int rc = nn_select(n);
+  if (rc) return rc;
+  NN_HIP(hipMemcpyAsync(n->mean, m.data(), 16 * sizeof(float), hipMemcpyHostToDevice, n->stream), "copy mean");
+  NN_HIP(hipMemcpyAsync(n->inv_std, is.data(), 16 * sizeof(float), hipMemcpyHostToDevice, n->stream), "copy std");
+  NN_HIP(hipMemcpyAsync(n->std_dev, s.data(), 16 * sizeof(float), hipMemcpyHostToDevice, n->stream), "copy std");
+  NN_HIP(hipStreamSynchronize(n->stream), "hipStreamSynchronize");
+  return LBM_OK;
+}
+
+int lbm_nn_forward(lbm_nn n, const float* x, float* y) {
+  if (!n || !x || !y) return nn_fail(LBM_EINVAL, "lbm_nn_forward: NULL argument");
+  int rc = nn_select(n);
+  if (rc) return rc;
+  if ((rc = nn_forward(n, x))) return rc;
+  NN_HIP(hipMemcpyAsync(y, n->y, sizeof(float) * (size_t)n->V * n->ch[n->L], hipMemcpyDeviceToDevice, n->stream),
+         "copy output");
+  return LBM_OK;
+}
+
+int lbm_nn_loss_backward(lbm_nn n, const float* x, const float* target, double* loss) {
+  if (!n || !x || !target) return nn_fail(LBM_EINVAL, "lbm_nn_loss_backward: NULL argument");
+  if (n->ch[n->L] > n->ch[0]) return nn_fail(LBM_EINVAL, "lbm_nn_loss_backward: more outputs than inputs");
+  int rc = nn_select(n);
+  if (rc) return rc;
+  if ((rc = nn_forward(n, x))) return rc;
+  const int V = n->V, C = n->ch[n->L];
+  const int lblocks = (V + 255) / 256;
+  hipLaunchKernelGGL(lbmnn::loss_kernel, dim3(lblocks), dim3(256), 0, n->stream, n->y, x, target, n->inv_std, C, V,
+                     n->dA, n->lpart);
+  NN_HIP(hipGetLastError(), "loss kernel");
+  // dA holds the gradient with respect to the output of layer l (pre-ReLU for l < L-1)
+  __bf16 *dcur = n->dA, *dnext = n->dB;
+  const int nchunks = V / n->chunk;
+  for (int l = n->L - 1; l >= 0; --l) {
+    const Layer& ly = n->layers[l];
+    const int wblocks = (27 * nchunks + 3) / 4;
+    if (ly.cinp == 16)
+      hipLaunchKernelGGL((lbmnn::wgrad_kernel<16>), dim3(wblocks), dim3(256), 0, n->stream, n->act[l], dcur, n->part,
+                         n->g, V, n->chunk);
+    else
+      hipLaunchKernelGGL((lbmnn::wgrad_kernel<32>), dim3(wblocks), dim3(256), 0, n->stream, n->act[l], dcur, n->part,
+                         n->g, V, n->chunk);
+    NN_HIP(hipGetLastError(), "weight gradient kernel");
+    const int ne = 27 * ly.cin * ly.cout;
+    hipLaunchKernelGGL(lbmnn::wgrad_reduce_kernel, dim3((ne + 255) / 256), dim3(256), 0, n->stream, n->part, nchunks,
+                       ly.cin, ly.cout, n->grads + ly.w_off);
+    NN_HIP(hipGetLastError(), "weight gradient reduction");
+    hipLaunchKernelGGL(lbmnn::bgrad_kernel, dim3(ly.cout), dim3(256), 0, n->stream, dcur, V, n->grads + ly.b_off);
+    NN_HIP(hipGetLastError(), "bias gradient kernel");
+    if (l > 0) {
+      // gradient with respect to this layer's input = previous output; times the ReLU derivative
+      NN_HIP((conv<32, false>(n, dcur, ly.wb, nullptr, 0, n->act[l], dnext, 32)), "conv backward-data");
+      __bf16* t = dcur;
+      dcur = dnext;
+      dnext = t;
+    }
+  }
+  if (loss) {
+    std::vector<double> h(lblocks);
+    NN_HIP(hipMemcpyAsync(h.data(), n->lpart, sizeof(double) * lblocks, hipMemcpyDeviceToHost, n->stream),
+           "copy loss");
+    NN_HIP(hipStreamSynchronize(n->stream), "hipStreamSynchronize");
+    double s = 0.0;
+    for (double x2 : h) s += x2;
+    *loss = s / ((double)C * V);
+  }
+  return LBM_OK;
+}
+
+int lbm_nn_adam_step(lbm_nn n, double lr, double beta1, double beta2, double eps, double grad_scale, int64_t t) {
+  if (!n) return nn_fail(LBM_EINVAL, "lbm_nn_adam_step: NULL network");
+  if (t < 1 || !(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0))
+    return nn_fail(LBM_EINVAL, "lbm_nn_adam_step: bad hyper-parameters");
+  int rc = nn_select(n);
+  if (rc) return rc;
+  const float c1 = (float)(1.0 / (1.0 - std::pow(beta1, (double)t)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow(beta2, (double)t)));
+  hipLaunchKernelGGL(lbmnn::adam_kernel, dim3((unsigned)((n->nparam + 255) / 256)), dim3(256), 0, n->stream,
+                     n->params, n->grads, n->m, n->v, n->nparam, (float)lr, (float)beta1, (float)beta2, (float)eps,
+                     (float)grad_scale, c1, c2);
+  NN_HIP(hipGetLastError(), "adam kernel");
+  return nn_pack_weights(n);
+}
+
+int lbm_nn_correct(lbm_nn n, lbm_handle h) {
+  if (!n || !h) return nn_fail(LBM_EINVAL, "lbm_nn_correct: NULL argument");
+  const int D = h->lattice;
+  if (n->ch[0] != D + 2 || n->ch[n->L] != D + 2)
+    return nn_fail(LBM_EINVAL, "lbm_nn_correct: the network must map D + 2 fields to D + 2 corrections");
+  if (h->n[0] != n->g.nx || h->n[1] != n->g.ny || h->n[2] != n->g.nz)
+    return nn_fail(LBM_EINVAL, "lbm_nn_correct: grid of the handle differs from the network's");
+  int rc = nn_select(n);
+  if (rc) return rc;
+  const int V = n->V;
+  double* rho = n->dfld;
+  double* u = rho + V;
+  double* T = u + 3 * (size_t)V;
+  double* drho = T + V;
+  double* du = drho + V;
+  double* dT = du + 3 * (size_t)V;
+  // the handle's stream orders moments, network and increments
+  hipStream_t saved = n->stream;
+  n->stream = h->stream;
+  if ((rc = lbm_moments(h, rho, u, T, LBM_DEVICE)) == LBM_OK) {
+    hipLaunchKernelGGL(lbmnn::fields_to_input_kernel, dim3((V + 255) / 256), dim3(256), 0, n->stream, rho, u, T, D, V,
+                       n->fld);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) rc = nn_hip(e, "fields kernel");
+    if (rc == LBM_OK) rc = nn_forward(n, n->fld);
+    if (rc == LBM_OK) {
+      hipLaunchKernelGGL(lbmnn::output_to_increments_kernel, dim3((V + 255) / 256), dim3(256), 0, n->stream, n->y,
+                         n->std_dev, D, V, drho, du, dT);
+      e = hipGetLastError();
+      if (e != hipSuccess) rc = nn_hip(e, "increments kernel");
+    }
+    if (rc == LBM_OK) rc = lbm_fields_add(h, drho, du, dT, LBM_DEVICE);
+  }
+  n->stream = saved;
+  return rc;
+}
+
+}  // extern "C"

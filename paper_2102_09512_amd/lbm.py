@@ -73,6 +73,22 @@ def _load():
     L.lbm_last_error.argtypes = [vp]
     L.lbm_last_error.restype = C.c_char_p
     L.lbm_device_copy.argtypes = [vp, vp, C.c_size_t, vp]
+    L.lbm_fields_add.argtypes = [vp, vp, vp, vp, C.c_int]
+    L.lbm_filter_moments.argtypes = [vp, C.c_int, vp, vp, vp, C.c_int]
+    L.lbm_nn_create.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(C.c_int), C.POINTER(i64)]
+    L.lbm_nn_destroy.argtypes = [vp]
+    L.lbm_nn_set_stream.argtypes = [vp, vp]
+    L.lbm_nn_param_count.argtypes = [vp]
+    L.lbm_nn_param_count.restype = i64
+    L.lbm_nn_set_params.argtypes = [vp, vp, C.c_int]
+    L.lbm_nn_get_params.argtypes = [vp, vp, C.c_int]
+    L.lbm_nn_get_grads.argtypes = [vp, vp, C.c_int]
+    L.lbm_nn_zero_grad.argtypes = [vp]
+    L.lbm_nn_set_scaling.argtypes = [vp, dp, dp]
+    L.lbm_nn_forward.argtypes = [vp, vp, vp]
+    L.lbm_nn_loss_backward.argtypes = [vp, vp, vp, dp]
+    L.lbm_nn_adam_step.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, i64]
+    L.lbm_nn_correct.argtypes = [vp, vp]
     L.lbm_batch_create.argtypes = [C.POINTER(vp), C.POINTER(vp), C.c_int]
     L.lbm_batch_destroy.argtypes = [vp]
     L.lbm_batch_set_stream.argtypes = [vp, vp]
@@ -83,7 +99,10 @@ def _load():
     for name in ("lbm_create", "lbm_destroy", "lbm_set_stream", "lbm_init_fields", "lbm_step", "lbm_moments",
                  "lbm_diagnostics", "lbm_get_state", "lbm_set_state", "lbm_device_copy", "lbm_batch_create",
                  "lbm_batch_destroy", "lbm_batch_set_stream", "lbm_batch_set_tile", "lbm_batch_get_tile",
-                 "lbm_batch_tune", "lbm_batch_step"):
+                 "lbm_batch_tune", "lbm_batch_step", "lbm_fields_add", "lbm_filter_moments", "lbm_nn_create",
+                 "lbm_nn_destroy", "lbm_nn_set_stream", "lbm_nn_set_params", "lbm_nn_get_params", "lbm_nn_get_grads",
+                 "lbm_nn_zero_grad", "lbm_nn_set_scaling", "lbm_nn_forward", "lbm_nn_loss_backward",
+                 "lbm_nn_adam_step", "lbm_nn_correct"):
         getattr(L, name).restype = C.c_int
     return L
 
@@ -289,3 +308,105 @@ def lbm_batch_tune(b, reps: int = 5) -> float:
 
 def lbm_batch_step(b, n: int = 1, graph_steps: int = 0) -> int:
     return _check(_L.lbm_batch_step(b, int(n), int(graph_steps)))
+
+
+# ---- coupling of coarse runs and the learned corrector ---------------------------
+
+def lbm_fields_add(h, drho, du, dT) -> int:
+    pr, kr, _a = _arg(drho)
+    pu, ku, _b = _arg(du)
+    pt, kt, _c = _arg(dT)
+    return _check(_L.lbm_fields_add(h, pr, pu, pt, _same_kind(kr, ku, kt)))
+
+
+def lbm_filter_moments(h, factor, rho, u, T):
+    """Writes the coarse moments into rho, u, T (numpy arrays or device tensors)."""
+    args = [_arg(x) for x in (rho, u, T)]
+    kind = _same_kind(*[a[1] for a in args])
+    _check(_L.lbm_filter_moments(h, int(factor), args[0][0], args[1][0], args[2][0], kind))
+    return rho, u, T
+
+
+def _f32(x):
+    """(pointer, kind, keep-alive) of an FP32 numpy array or tensor."""
+    if _is_torch(x):
+        return _arg(x, dtype=np.float32)
+    a = np.ascontiguousarray(x, dtype=np.float32)
+    return a.ctypes.data, LBM_HOST, a
+
+
+def lbm_nn_create(channels, dims) -> int:
+    ch = (C.c_int * len(channels))(*[int(c) for c in channels])
+    d = (C.c_int64 * 3)(*[int(v) for v in (list(dims) + [1] * (3 - len(dims)))])
+    n = C.c_void_p()
+    _check(_L.lbm_nn_create(C.byref(n), len(channels) - 1, ch, d))
+    return n.value
+
+
+def lbm_nn_destroy(n) -> int:
+    return _check(_L.lbm_nn_destroy(n))
+
+
+def lbm_nn_set_stream(n, stream) -> int:
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    return _check(_L.lbm_nn_set_stream(n, stream))
+
+
+def lbm_nn_param_count(n) -> int:
+    return int(_L.lbm_nn_param_count(n))
+
+
+def lbm_nn_set_params(n, params) -> int:
+    p, k, _keep = _f32(params)
+    return _check(_L.lbm_nn_set_params(n, p, k))
+
+
+def lbm_nn_get_params(n) -> np.ndarray:
+    out = np.zeros(lbm_nn_param_count(n), dtype=np.float32)
+    _check(_L.lbm_nn_get_params(n, out.ctypes.data, LBM_HOST))
+    return out
+
+
+def lbm_nn_get_grads(n) -> np.ndarray:
+    out = np.zeros(lbm_nn_param_count(n), dtype=np.float32)
+    _check(_L.lbm_nn_get_grads(n, out.ctypes.data, LBM_HOST))
+    return out
+
+
+def lbm_nn_zero_grad(n) -> int:
+    return _check(_L.lbm_nn_zero_grad(n))
+
+
+def lbm_nn_set_scaling(n, mean, std) -> int:
+    m = np.ascontiguousarray(mean, dtype=np.float64)
+    s = np.ascontiguousarray(std, dtype=np.float64)
+    return _check(_L.lbm_nn_set_scaling(n, m.ctypes.data_as(C.POINTER(C.c_double)),
+                                        s.ctypes.data_as(C.POINTER(C.c_double))))
+
+
+def lbm_nn_forward(n, x, y) -> int:
+    """x, y: contiguous float32 device tensors (planes)."""
+    px, kx, _a = _arg(x, dtype=np.float32)
+    py, ky, _b = _arg(y, dtype=np.float32)
+    if kx != LBM_DEVICE or ky != LBM_DEVICE:
+        raise ValueError("lbm_nn_forward takes device tensors")
+    return _check(_L.lbm_nn_forward(n, px, py))
+
+
+def lbm_nn_loss_backward(n, x, target) -> float:
+    px, kx, _a = _arg(x, dtype=np.float32)
+    pt, kt, _b = _arg(target, dtype=np.float32)
+    if kx != LBM_DEVICE or kt != LBM_DEVICE:
+        raise ValueError("lbm_nn_loss_backward takes device tensors")
+    loss = C.c_double()
+    _check(_L.lbm_nn_loss_backward(n, px, pt, C.byref(loss)))
+    return loss.value
+
+
+def lbm_nn_adam_step(n, lr, beta1=0.9, beta2=0.999, eps=1e-8, grad_scale=1.0, t=1) -> int:
+    return _check(_L.lbm_nn_adam_step(n, float(lr), float(beta1), float(beta2), float(eps), float(grad_scale), int(t)))
+
+
+def lbm_nn_correct(n, h) -> int:
+    return _check(_L.lbm_nn_correct(n, h))

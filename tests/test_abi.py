@@ -1,4 +1,4 @@
-"""The C-ABI library loads and exports every entry point of include/lbm.h,
+"""The C-ABI library loads and exports every entry point of include/*.h,
 and its host-side argument checks answer before any device work (runs
 without a GPU)."""
 import ctypes as C
@@ -11,9 +11,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+    names = set()
+    for hdr in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if hdr.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", hdr)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -93,3 +97,24 @@ def test_batch_null_arguments_fail_cleanly(lbm):
     assert L.lbm_batch_step(None, 1, 0) == lbm.LBM_EINVAL
     assert L.lbm_batch_tune(None, 1, None) == lbm.LBM_EINVAL
     assert L.lbm_batch_set_stream(None, None) == lbm.LBM_EINVAL
+
+
+@pytest.mark.parametrize("channels,dims,needle", [
+    ([5, 32, 5], (8, 8, 2), "multiple of 256"),
+    ([20, 32, 5], (8, 8, 8), "input channels"),
+    ([5, 16, 5], (8, 8, 8), "hidden widths"),
+    ([5, 32, 40], (8, 8, 8), "output channels"),
+])
+def test_nn_create_rejects_bad_shapes(lbm, channels, dims, needle):
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_nn_create(channels, dims)
+    assert e.value.code == lbm.LBM_EINVAL and needle in str(e.value)
+
+
+def test_coupling_null_arguments_fail_cleanly(lbm):
+    L = lbm.raw()
+    assert L.lbm_fields_add(None, None, None, None, 0) == lbm.LBM_EINVAL
+    assert L.lbm_filter_moments(None, 2, None, None, None, 0) == lbm.LBM_EINVAL
+    assert L.lbm_nn_destroy(None) == lbm.LBM_OK
+    assert L.lbm_nn_correct(None, None) == lbm.LBM_EINVAL
+    assert L.lbm_nn_param_count(None) == -1

@@ -1,0 +1,260 @@
+"""The learned corrector's kernels against the FP64 reference network
+(oracle/convnet.py): forward, loss and gradients on bf16 matrix cores (FP32
+accumulation), the Adam step, training on a toy problem; and the coupling to
+the lattice Boltzmann library: field increments by re-equilibration and the
+conservative box filter against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import convnet as N
+from paper_2102_09512_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CH = [5, 32, 32, 32, 5]
+
+
+def _lbm():
+    from paper_2102_09512_amd import lbm
+
+    return lbm
+
+
+def _params(seed, channels=CH, gain=1.0):
+    """He-scaled random weights, small biases."""
+    r = np.random.default_rng(seed)
+    out = []
+    for l in range(len(channels) - 1):
+        ci, co = channels[l], channels[l + 1]
+        out.append(r.normal(0.0, gain * np.sqrt(2.0 / (27 * ci)), 27 * ci * co))
+        out.append(r.normal(0.0, 0.01, co))
+    return np.concatenate(out)
+
+
+def _fields(shape, seed):
+    r = np.random.default_rng(seed)
+    x = np.empty((5,) + shape)
+    x[0] = 1.0 + 0.05 * r.normal(size=shape)
+    x[1:4] = 0.1 * r.normal(size=(3,) + shape)
+    x[4] = 0.15 + 0.01 * r.normal(size=shape)
+    return x
+
+
+MEAN = np.array([1.0, 0.0, 0.0, 0.0, 0.15])
+STD = np.array([0.05, 0.1, 0.1, 0.1, 0.01])
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def test_forward_matches_reference():
+    lbm = _lbm()
+    shape = (8, 8, 8)
+    p = _params(1)
+    x = _fields(shape, 2)
+    n = lbm.lbm_nn_create(CH, shape[::-1])
+    try:
+        lbm.lbm_nn_set_params(n, p.astype(np.float32))
+        lbm.lbm_nn_set_scaling(n, MEAN, STD)
+        xd = torch.from_numpy(x.astype(np.float32)).cuda()
+        yd = torch.zeros((5,) + shape, dtype=torch.float32, device="cuda")
+        lbm.lbm_nn_forward(n, xd, yd)
+        torch.cuda.synchronize()
+        y = yd.cpu().numpy()
+    finally:
+        lbm.lbm_nn_destroy(n)
+    ref, _ = N.forward(p, CH, (x - MEAN[:, None, None, None]) / STD[:, None, None, None])
+    e = _rel(y, ref)
+    print(f"  forward: max error {e:.2e} of max |y| {np.abs(ref).max():.3f}", flush=True)
+    assert e < 3e-2  # bf16 operands (8-bit mantissa) through four layers
+
+
+def test_loss_and_gradients_match_reference():
+    lbm = _lbm()
+    shape = (8, 8, 16)
+    p = _params(3)
+    x = _fields(shape, 4)
+    t = x + 0.3 * STD[:, None, None, None] * np.random.default_rng(5).normal(size=x.shape)
+    n = lbm.lbm_nn_create(CH, shape[::-1])
+    try:
+        lbm.lbm_nn_set_params(n, p.astype(np.float32))
+        lbm.lbm_nn_set_scaling(n, MEAN, STD)
+        lbm.lbm_nn_zero_grad(n)
+        loss = lbm.lbm_nn_loss_backward(n, torch.from_numpy(x.astype(np.float32)).cuda(),
+                                        torch.from_numpy(t.astype(np.float32)).cuda())
+        g = lbm.lbm_nn_get_grads(n).astype(np.float64)
+    finally:
+        lbm.lbm_nn_destroy(n)
+    ref_loss, ref_g = N.loss_and_grad(p, CH, x, t, MEAN, STD)
+    print(f"  loss {loss:.6e} reference {ref_loss:.6e}", flush=True)
+    assert loss == pytest.approx(ref_loss, rel=2e-2)
+    off = 0
+    for l in range(len(CH) - 1):
+        for size, name in ((27 * CH[l] * CH[l + 1], "W"), (CH[l + 1], "b")):
+            a, b = g[off: off + size], ref_g[off: off + size]
+            off += size
+            cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+            print(f"  layer {l} {name}: max error {_rel(a, b):.2e}, cosine {cos:.6f}", flush=True)
+            assert cos > 0.999 and _rel(a, b) < 5e-2
+
+
+def test_adam_step_matches_reference():
+    lbm = _lbm()
+    shape = (8, 8, 8)
+    p = _params(6)
+    x = _fields(shape, 7)
+    t = x * 1.01
+    n = lbm.lbm_nn_create(CH, shape[::-1])
+    try:
+        lbm.lbm_nn_set_params(n, p.astype(np.float32))
+        lbm.lbm_nn_set_scaling(n, MEAN, STD)
+        lbm.lbm_nn_zero_grad(n)
+        lbm.lbm_nn_loss_backward(n, torch.from_numpy(x.astype(np.float32)).cuda(),
+                                 torch.from_numpy(t.astype(np.float32)).cuda())
+        g = lbm.lbm_nn_get_grads(n).astype(np.float64)
+        lbm.lbm_nn_adam_step(n, 1e-3, 0.9, 0.999, 1e-8, 0.5, 1)
+        lbm.lbm_nn_adam_step(n, 1e-3, 0.9, 0.999, 1e-8, 0.5, 2)
+        q = lbm.lbm_nn_get_params(n).astype(np.float64)
+    finally:
+        lbm.lbm_nn_destroy(n)
+    ref = p.astype(np.float32).astype(np.float64)
+    m, v = np.zeros_like(ref), np.zeros_like(ref)
+    for step in (1, 2):
+        N.adam_step(ref, 0.5 * g, m, v, 1e-3, 0.9, 0.999, 1e-8, step)
+    assert np.abs(q - ref).max() < 1e-6
+
+
+def test_training_reduces_the_loss():
+    """A target that is a fixed smooth function of the input: the network
+    learns it (the loss falls tenfold in 150 Adam steps on one sample set)."""
+    lbm = _lbm()
+    shape = (8, 8, 16)
+    xs, ts = [], []
+    for s in range(4):
+        rho, u, T = I.smooth_random(3, shape[::-1], seed=30 + s, u_amp=0.1)
+        x = np.concatenate([rho[None], u, T[None]])
+        t = x.copy()
+        t[4] += 0.3 * STD[4] * np.tanh((x[0] - 1.0) / STD[0])  # T nudged by the local density
+        t[1] += 0.3 * STD[1] * (np.roll(x[2], 1, axis=2) - x[2]) / STD[2]
+        xs.append(torch.from_numpy(x.astype(np.float32)).cuda())
+        ts.append(torch.from_numpy(t.astype(np.float32)).cuda())
+    n = lbm.lbm_nn_create(CH, shape[::-1])
+    try:
+        lbm.lbm_nn_set_params(n, _params(8, gain=0.5).astype(np.float32))
+        lbm.lbm_nn_set_scaling(n, MEAN, STD)
+        losses = []
+        for it in range(1, 151):
+            lbm.lbm_nn_zero_grad(n)
+            losses.append(sum(lbm.lbm_nn_loss_backward(n, x, t) for x, t in zip(xs, ts)) / len(xs))
+            lbm.lbm_nn_adam_step(n, 2e-3, 0.9, 0.999, 1e-8, 1.0 / len(xs), it)
+        print(f"  loss {losses[0]:.3e} -> {losses[-1]:.3e}", flush=True)
+        assert losses[-1] < 0.1 * losses[0]
+    finally:
+        lbm.lbm_nn_destroy(n)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_fields_add_matches_reference(fp32):
+    """The state changes by f^eq(new) - f^eq(old) (and g likewise) node by
+    node, computed here by the oracle's nodal equilibria from the moments the
+    library reports; the new moments are the old ones plus the increments."""
+    lbm = _lbm()
+    dims = (6, 5, 4)
+    rho, u, T = I.smooth_random(3, dims, seed=9, u_amp=0.05)
+    h = lbm.lbm_create(3, dims, 1.4, 0.7, 0.02, precision=lbm.LBM_FP32_DEV if fp32 else lbm.LBM_FP64,
+                       visc_exponent=0.76, T_ref=0.15)
+    r = np.random.default_rng(10)
+    drho = 0.01 * r.normal(size=rho.shape)
+    du = 0.01 * r.normal(size=u.shape)
+    dT = 0.002 * r.normal(size=T.shape)
+    try:
+        lbm.lbm_init_fields(h, rho, u, T)
+        lbm.lbm_step(h, 5)  # some non-equilibrium content
+        nb = lbm.lbm_state_bytes(h)
+        before = np.zeros(nb // (4 if fp32 else 8), dtype=np.float32 if fp32 else np.float64)
+        lbm.lbm_get_state(h, before)
+        m0 = [np.zeros(a.shape) for a in (rho, u, T)]
+        lbm.lbm_moments(h, *m0)
+        lbm.lbm_fields_add(h, drho, du, dT)
+        after = np.zeros_like(before)
+        lbm.lbm_get_state(h, after)
+        m1 = [np.zeros(a.shape) for a in (rho, u, T)]
+        lbm.lbm_moments(h, *m1)
+    finally:
+        lbm.lbm_destroy(h)
+    Q, Nn, Cv = 27, rho.size, 2.5
+    r0, u0, T0 = m0[0].reshape(-1), m0[1].reshape(3, -1), m0[2].reshape(-1)
+    rn, un, Tn = r0 + drho.reshape(-1), u0 + du.reshape(3, -1), T0 + dT.reshape(-1)
+    ref = np.zeros((2 * Q, Nn))
+    for k in range(Nn):
+        ref[:Q, k] = oracle.feq(3, rn[k], un[:, k], Tn[k]) - oracle.feq(3, r0[k], u0[:, k], T0[k])
+        ref[Q:, k] = oracle.geq(3, rn[k], un[:, k], Tn[k], Cv) - oracle.geq(3, r0[k], u0[:, k], T0[k], Cv)
+    got = after.astype(np.float64).reshape(2 * Q, Nn) - before.astype(np.float64).reshape(2 * Q, Nn)
+    if fp32:  # one rounding of each stored float
+        tol = 1e-6 * np.abs(ref).max() + 2.0 ** -23 * np.abs(after).max()
+    else:
+        tol = 1e-12 * np.abs(ref).max()
+    e = float(np.abs(got - ref).max())
+    print(f"  state increment error {e:.2e} (bound {tol:.2e})", flush=True)
+    assert e <= tol
+    mt = 2e-6 if fp32 else 1e-13
+    assert np.abs(m1[0] - (m0[0] + drho)).max() < mt
+    assert np.abs(m1[1] - (m0[1] + du)).max() < mt
+    assert np.abs(m1[2] - (m0[2] + dT)).max() < mt
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_filter_moments_matches_reference(D):
+    lbm = _lbm()
+    dims = (16, 12, 8) if D == 3 else (16, 12)
+    rho, u, T = I.smooth_random(D, dims, seed=11, u_amp=0.05)
+    h = lbm.lbm_create(D, dims, 1.4, 0.7, 0.02)
+    try:
+        lbm.lbm_init_fields(h, rho, u, T)
+        lbm.lbm_step(h, 3)
+        mom = [np.zeros(a.shape) for a in (rho, u, T)]
+        lbm.lbm_moments(h, *mom)
+        f = 4
+        cshape = (dims[2] // f if D == 3 else 1, dims[1] // f, dims[0] // f)
+        out = (np.zeros(cshape), np.zeros((D,) + cshape), np.zeros(cshape))
+        lbm.lbm_filter_moments(h, f, *out)
+    finally:
+        lbm.lbm_destroy(h)
+    ref = N.box_filter(mom[0], mom[1], mom[2], 4, 2.5)
+    for a, b in zip(out, ref):
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+
+
+def test_correct_adds_the_network_output():
+    """lbm_nn_correct = moments -> network -> increments std * y -> fields_add."""
+    lbm = _lbm()
+    dims = (8, 8, 8)
+    rho, u, T = I.smooth_random(3, dims, seed=12, u_amp=0.05)
+    h = lbm.lbm_create(3, dims, 1.4, 0.7, 0.02, precision=lbm.LBM_FP32_DEV, visc_exponent=0.76, T_ref=0.15)
+    n = lbm.lbm_nn_create(CH, dims)
+    try:
+        lbm.lbm_nn_set_params(n, (0.3 * _params(13)).astype(np.float32))
+        lbm.lbm_nn_set_scaling(n, MEAN, STD)
+        lbm.lbm_init_fields(h, rho, u, T)
+        lbm.lbm_step(h, 2)
+        before = [np.zeros(a.shape) for a in (rho, u, T)]
+        lbm.lbm_moments(h, *before)
+        x = np.concatenate([before[0][None], before[1], before[2][None]]).astype(np.float32)
+        yd = torch.zeros(x.shape, dtype=torch.float32, device="cuda")
+        lbm.lbm_nn_forward(n, torch.from_numpy(x).cuda(), yd)
+        torch.cuda.synchronize()
+        y = yd.cpu().numpy().astype(np.float64)
+        lbm.lbm_nn_correct(n, h)
+        after = [np.zeros(a.shape) for a in (rho, u, T)]
+        lbm.lbm_moments(h, *after)
+    finally:
+        lbm.lbm_nn_destroy(n)
+        lbm.lbm_destroy(h)
+    assert np.abs(after[0] - (before[0] + STD[0] * y[0])).max() < 1e-6
+    assert np.abs(after[1] - (before[1] + STD[1:4, None, None, None] * y[1:4])).max() < 1e-6
+    assert np.abs(after[2] - (before[2] + STD[4] * y[4])).max() < 1e-6
+    assert np.abs(STD[4] * y[4]).max() > 1e-5  # the correction is not trivially zero
