@@ -147,6 +147,9 @@ const char* lbm_last_error(lbm_handle h);
    moments become (rho', u', T').  Arrays as in lbm_init_fields; LBM_EINVAL if
    a new rho or T is not positive (nothing changed then). */
 int lbm_fields_add(lbm_handle h, const double* drho, const double* du, const double* dT, int mem);
+/* As lbm_fields_add with the new fields given instead of increments: the
+   moments become (rho, u, T) and the non-equilibrium parts are kept. */
+int lbm_fields_set(lbm_handle h, const double* rho, const double* u, const double* T, int mem);
 /* Box filter of the stored moments onto the coarse grid of factor^D times
    fewer nodes (every dim divisible by factor; for D2Q9 the z factor is 1):
    rho_c = mean rho, (rho u)_c = mean rho u, (rho E)_c = mean rho E, and

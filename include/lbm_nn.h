@@ -20,7 +20,8 @@
  *
  * Scaling.  The network sees normalised inputs (x_c - mean_c) / std_c and its
  * output is a normalised correction: the correction in physical units is
- * y_c * std_c (lbm_nn_set_scaling; c < c[0], and c[L] = c[0] for a corrector).
+ * y_c * out_std_c (lbm_nn_set_scaling; c < c[0] for the input, c < c[L] for
+ * the output; c[L] = c[0] for a corrector).
  *
  * Errors as in lbm.h (LBM_OK or a negative code, message in lbm_last_error).
  */
@@ -52,20 +53,28 @@ int lbm_nn_get_params(lbm_nn net, float* params, int mem);
    lbm_nn_zero_grad, same layout as the parameters. */
 int lbm_nn_get_grads(lbm_nn net, float* grads, int mem);
 int lbm_nn_zero_grad(lbm_nn net);
-/* mean[c], std[c] (host arrays of c[0] values, std > 0). */
-int lbm_nn_set_scaling(lbm_nn net, const double* mean, const double* std);
+/* mean[c], std[c] (host arrays of c[0] values, std > 0) normalise the input;
+   out_std[c] (host array of c[L] values, > 0) scales the output; out_std may
+   be NULL, then out_std = std. */
+int lbm_nn_set_scaling(lbm_nn net, const double* mean, const double* std, const double* out_std);
 /* y = network(normalised x): x is c[0] planes, y is c[L] planes (device). */
 int lbm_nn_forward(lbm_nn net, const float* x, float* y);
 /* Training loss of one sample and its gradients (accumulated):
-     L = mean over nodes and c < c[L] of (y_c + (x_c - t_c) / std_c)^2,
+     L = mean over nodes and c < c[L] of (y_c + (x_c - t_c) / out_std_c)^2,
    y = network(normalised x), t the target fields (c[L] planes, device); the
-   corrected field x_c + y_c std_c is compared with t_c in normalised units.
+   corrected field x_c + y_c out_std_c is compared with t_c in units of
+   out_std_c.
    *loss (host, may be NULL) receives L.  Synchronous. */
 int lbm_nn_loss_backward(lbm_nn net, const float* x, const float* target, double* loss);
 /* One Adam step on the accumulated gradients (scaled by grad_scale), step
    count t >= 1 for the bias correction; then the bf16 weight copies are
    rebuilt. */
 int lbm_nn_adam_step(lbm_nn net, double lr, double beta1, double beta2, double eps, double grad_scale, int64_t t);
+/* FP64 fields (device) -> FP32 planes x[c][v] (device) for the network:
+   c = 0 rho, 1..D u (u holds D planes of nodes values), D + 1 T.  nodes >= 1.
+   Runs on hip_stream. */
+int lbm_nn_fields_to_planes(int D, int64_t nodes, const double* rho, const double* u, const double* T, float* x,
+                            void* hip_stream);
 /* Applies the corrector to a lattice Boltzmann handle whose dims equal the
    network's: reads rho, u, T (lbm_moments), runs the network and adds the
    correction with lbm_fields_add.  Requires c[0] = c[L] = D + 2. */

@@ -7,11 +7,18 @@ Network: layer l maps c[l] channels to c[l+1]:
     y[o](v) = b[o] + sum_t sum_i x[i](v + s_t) W[t][i][o],
 s_t = (t%3 - 1, (t//3)%3 - 1, t//9 - 1) in (x, y, z), periodic; ReLU after
 every layer but the last.  Arrays are [channel][z][y][x].  The training loss of
-one sample is L = mean over nodes and channels of (y_c + (x_c - t_c)/std_c)^2
-with y = network((x - mean)/std).
+one sample is L = mean over nodes and channels of (y_c + (x_c - t_c)/s_c)^2
+with y = network((x - mean)/std) and s the output scale (s = std unless given).
 
 Everything is written out with numpy in FP64; the backward pass follows the
 chain rule layer by layer and is pinned by finite differences in the tests.
+
+Optional storage rounding (store=bf16): the library keeps the network's
+matrix-core operands in bfloat16 (normalised inputs, weights, hidden
+activations, the loss gradient and the gradients passed between layers) and
+accumulates in FP32.  With store=bf16 those values are rounded to bfloat16
+where the library stores them, and everything else stays FP64, so the
+comparison isolates what the format itself costs from accumulation order.
 """
 from __future__ import annotations
 
@@ -24,6 +31,21 @@ def shift(a, t, sign=1):
     """a moved so that out(v) = a(v + sign * s_t), periodic (last three axes z, y, x)."""
     dx, dy, dz = TAPS[t]
     return np.roll(a, shift=(-sign * dz, -sign * dy, -sign * dx), axis=(-3, -2, -1))
+
+
+def bf16(a):
+    """Round to the nearest bfloat16 (1 sign, 8 exponent, 7 fraction bits),
+    ties to even, via the FP32 bit pattern (the value is first rounded to
+    FP32); returned as FP64."""
+    a = np.asarray(a, dtype=np.float32)
+    bits = a.view(np.uint32).astype(np.uint64)
+    keep = (bits >> 16) & 1  # lowest kept bit: ties go to the even neighbour
+    r = ((bits + 0x7FFF + keep) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _same(a):
+    return a
 
 
 def unpack(params, channels):
@@ -52,28 +74,31 @@ def conv(x, W, b):
     return y + b[:, None, None, None]
 
 
-def forward(params, channels, xn):
+def forward(params, channels, xn, store=None):
     """Network output for a normalised input; also the list of layer inputs."""
+    store = store or _same
     layers = unpack(params, channels)
-    h, inputs = np.asarray(xn, dtype=np.float64), []
+    h, inputs = store(np.asarray(xn, dtype=np.float64)), []
     for l, (W, b) in enumerate(layers):
         inputs.append(h)
-        pre = conv(h, W, b)
-        h = pre if l == len(layers) - 1 else np.maximum(pre, 0.0)
+        pre = conv(h, store(W), b)
+        h = pre if l == len(layers) - 1 else store(np.maximum(pre, 0.0))
     return h, inputs
 
 
-def loss_and_grad(params, channels, x, target, mean, std):
+def loss_and_grad(params, channels, x, target, mean, std, store=None, out_std=None):
     """Loss of one sample and its gradient with respect to the parameters."""
+    store = store or _same
     mean = np.asarray(mean, dtype=np.float64)[:, None, None, None]
     std = np.asarray(std, dtype=np.float64)[:, None, None, None]
     x = np.asarray(x, dtype=np.float64)
     C = channels[-1]
-    y, inputs = forward(params, channels, (x - mean) / std)
-    r = y + (x[:C] - np.asarray(target, dtype=np.float64)) / std[:C]
+    y, inputs = forward(params, channels, (x - mean) / std, store)
+    s = std[:C] if out_std is None else np.asarray(out_std, dtype=np.float64)[:, None, None, None]
+    r = y + (x[:C] - np.asarray(target, dtype=np.float64)) / s
     V = r[0].size
     loss = float((r ** 2).sum() / (C * V))
-    d = 2.0 * r / (C * V)  # dL/dy
+    d = store(2.0 * r / (C * V))  # dL/dy
     layers = unpack(params, channels)
     grads = []
     for l in range(len(layers) - 1, -1, -1):
@@ -85,9 +110,10 @@ def loss_and_grad(params, channels, x, target, mean, std):
         if l > 0:
             # dL/dh(v) = sum_t sum_o d[o](v - s_t) W[t][i][o], then the ReLU that produced h
             dh = np.zeros(h.shape)
+            Ws = store(W)
             for t in range(27):
-                dh += np.einsum("ozyx,io->izyx", shift(d, t, sign=-1), W[t])
-            d = dh * (h > 0.0)
+                dh += np.einsum("ozyx,io->izyx", shift(d, t, sign=-1), Ws[t])
+            d = store(dh * (h > 0.0))
     g = []
     for dW, db in reversed(grads):
         g.append(dW.ravel())

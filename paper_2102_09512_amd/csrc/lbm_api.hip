@@ -417,12 +417,13 @@ int lbm_set_state(lbm_handle h, const void* buf, size_t bytes, int mem, int64_t 
 
 int64_t lbm_step_count(lbm_handle h) { return h ? h->step : -1; }
 
-int lbm_fields_add(lbm_handle h, const double* drho, const double* du, const double* dT, int mem) {
-  if (!h) return fail(LBM_EINVAL, "lbm_fields_add: NULL handle");
-  if (!drho || !du || !dT) return fail(LBM_EINVAL, "lbm_fields_add: NULL increment");
-  if (mem != LBM_HOST && mem != LBM_DEVICE) return fail(LBM_EINVAL, "lbm_fields_add: bad memory kind");
+static int fields_update(lbm_handle h, const double* drho, const double* du, const double* dT, int mem, bool keep,
+                         const char* name) {
+  if (!h) return fail(LBM_EINVAL, std::string(name) + ": NULL handle");
+  if (!drho || !du || !dT) return fail(LBM_EINVAL, std::string(name) + ": NULL field");
+  if (mem != LBM_HOST && mem != LBM_DEVICE) return fail(LBM_EINVAL, std::string(name) + ": bad memory kind");
   Ctx* c = h;
-  if (!c->initialised) return fail(LBM_ESTATE, "lbm_fields_add: no state (lbm_init_fields)");
+  if (!c->initialised) return fail(LBM_ESTATE, std::string(name) + ": no state (lbm_init_fields)");
   int rc = select_device(c);
   if (rc) return rc;
   if ((rc = ensure_scratch(c))) return rc;
@@ -440,15 +441,23 @@ int lbm_fields_add(lbm_handle h, const double* drho, const double* du, const dou
     dT = st + 4 * N;
   }
   HIP_OR_FAIL(lbm::launch_fields(*c, c->buf[c->cur], c->fields), "moments kernel");
-  HIP_OR_FAIL(lbm::launch_fields_plus(*c, c->fields, drho, du, dT, newf), "increment kernel");
+  HIP_OR_FAIL(lbm::launch_fields_plus(*c, c->fields, drho, du, dT, newf, keep), "increment kernel");
   HIP_OR_FAIL(lbm::launch_validate(*c, newf, newf + N, newf + 4 * N, c->partial, c->partial_blocks, c->diag_dev),
               "validate");
   double bad = 0.0;
   HIP_OR_FAIL(hipMemcpyAsync(&bad, c->diag_dev, sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy count");
   HIP_OR_FAIL(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
-  if (bad != 0.0) return fail(LBM_EINVAL, "lbm_fields_add: non-finite value or rho <= 0 or T <= 0 after the increment");
+  if (bad != 0.0) return fail(LBM_EINVAL, std::string(name) + ": non-finite value or rho <= 0 or T <= 0 in the new fields");
   HIP_OR_FAIL(lbm::launch_fields_add(*c, c->buf[c->cur], c->fields, newf), "re-equilibration kernel");
   return LBM_OK;
+}
+
+int lbm_fields_add(lbm_handle h, const double* drho, const double* du, const double* dT, int mem) {
+  return fields_update(h, drho, du, dT, mem, true, "lbm_fields_add");
+}
+
+int lbm_fields_set(lbm_handle h, const double* rho, const double* u, const double* T, int mem) {
+  return fields_update(h, rho, u, T, mem, false, "lbm_fields_set");
 }
 
 int lbm_filter_moments(lbm_handle h, int factor, double* rho, double* u, double* T, int mem) {

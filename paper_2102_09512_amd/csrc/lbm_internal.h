@@ -109,7 +109,7 @@ hipError_t launch_unpack(const Ctx& c, const void* state, void* pops);
 int set_error(int code, const std::string& msg);
 hipError_t launch_fields_add(const Ctx& c, void* pops, const double* oldf, const double* newf);
 hipError_t launch_fields_plus(const Ctx& c, const double* oldf, const double* drho, const double* du, const double* dT,
-                              double* newf);
+                              double* newf, bool keep);
 hipError_t launch_filter(const Ctx& c, const double* fields, int factor, double* rho, double* u, double* T);
 hipError_t launch_batch_step(const Batch& b, hipStream_t s, int flip);
 hipError_t launch_toggle(const Batch& b, hipStream_t s);

@@ -831,15 +831,17 @@ __global__ void __launch_bounds__(256) fields_add_kernel(S* __restrict__ pops, c
   }
 }
 
-// new = old + increments (rho, u planes, T); increments d: drho[N], du[D N], dT[N]
+// new = keep * old + d (rho, u planes, T); d: drho[N], du[D N], dT[N]; keep is
+// 1 (increments) or 0 (new values; u_z of a 2-D lattice stays 0)
 __global__ void __launch_bounds__(256) fields_plus_kernel(const double* __restrict__ oldf, const double* __restrict__ drho,
                                                           const double* __restrict__ du, const double* __restrict__ dT,
-                                                          double* __restrict__ newf, long long N, int D) {
+                                                          double* __restrict__ newf, long long N, int D, int keep) {
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
-  newf[n] = oldf[n] + drho[n];
-  for (int a = 0; a < 3; ++a) newf[(1 + a) * N + n] = oldf[(1 + a) * N + n] + (a < D ? du[a * N + n] : 0.0);
-  newf[4 * N + n] = oldf[4 * N + n] + dT[n];
+  const double k = keep ? 1.0 : 0.0;
+  newf[n] = k * oldf[n] + drho[n];
+  for (int a = 0; a < 3; ++a) newf[(1 + a) * N + n] = k * oldf[(1 + a) * N + n] + (a < D ? du[a * N + n] : 0.0);
+  newf[4 * N + n] = k * oldf[4 * N + n] + dT[n];
 }
 
 // coarse node: means of rho, rho u and rho E over its factor^D fine nodes
@@ -895,10 +897,10 @@ hipError_t launch_fields_add(const Ctx& c, void* pops, const double* oldf, const
 }
 
 hipError_t launch_fields_plus(const Ctx& c, const double* oldf, const double* drho, const double* du, const double* dT,
-                              double* newf) {
+                              double* newf, bool keep) {
   const long long N = c.N;
   hipLaunchKernelGGL(fields_plus_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, c.stream, oldf, drho, du, dT,
-                     newf, N, c.lattice);
+                     newf, N, c.lattice, keep ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(256) bgrad_kernel(const __bf16* __restrict__ d
   if (threadIdx.x == 0) grad_b[o] += red[0];
 }
 
-// r = y + (x - target) / std; loss partial sums of r^2; dout[v][c] = 2 r / (C V)
+// r = y + (x - target) / out_std; loss partial sums of r^2; dout[v][c] = 2 r / (C V)
 __global__ void __launch_bounds__(256) loss_kernel(const float* __restrict__ y, const float* __restrict__ x,
                                                    const float* __restrict__ tgt, const float* __restrict__ inv_std,
                                                    int C, int V, __bf16* __restrict__ dout, double* __restrict__ partial) {
@@ -275,8 +275,8 @@ struct lbm_nn_ctx {
   std::vector<Layer> layers;
   long long nparam = 0;
   float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
-  float *mean = nullptr, *inv_std = nullptr, *std_dev = nullptr;  // device, 16 each
-  std::vector<double> std_host;
+  float *mean = nullptr, *inv_std = nullptr;          // input scaling (device, 16 each)
+  float *out_std = nullptr, *inv_out_std = nullptr;   // output scaling (device, 32 each)
   std::vector<__bf16*> act;     // act[l]: input of layer l (bf16 [V][16 or 32]); act[L] unused
   __bf16 *dA = nullptr, *dB = nullptr;  // gradient ping-pong, bf16 [V][32]
   float* y = nullptr;                   // network output planes [c_L][V]
@@ -373,7 +373,6 @@ int lbm_nn_create(lbm_nn* out, int layers, const int* channels, const int64_t di
     n->layers.push_back(ly);
   }
   n->nparam = off;
-  n->std_host.assign(16, 1.0);
   int rc = LBM_OK;
   auto alloc = [&](void** p, size_t bytes) {
     if (rc != LBM_OK) return;
@@ -389,7 +388,8 @@ int lbm_nn_create(lbm_nn* out, int layers, const int* channels, const int64_t di
   alloc((void**)&n->v, P);
   alloc((void**)&n->mean, 16 * sizeof(float));
   alloc((void**)&n->inv_std, 16 * sizeof(float));
-  alloc((void**)&n->std_dev, 16 * sizeof(float));
+  alloc((void**)&n->out_std, 32 * sizeof(float));
+  alloc((void**)&n->inv_out_std, 32 * sizeof(float));
   n->act.assign(layers, nullptr);
   for (int l = 0; l < layers; ++l) alloc((void**)&n->act[l], sizeof(__bf16) * (size_t)V * (l == 0 ? 16 : 32));
   alloc((void**)&n->dA, sizeof(__bf16) * (size_t)V * 32);
@@ -405,14 +405,15 @@ int lbm_nn_create(lbm_nn* out, int layers, const int* channels, const int64_t di
     alloc((void**)&ly.wb, sizeof(__bf16) * 27 * 32 * 32);
   }
   if (rc == LBM_OK) {
-    std::vector<float> mean(16, 0.f), one(16, 1.f);
+    std::vector<float> mean(16, 0.f), one(32, 1.f);
     hipError_t e = hipMemset(n->params, 0, P);
     if (e == hipSuccess) e = hipMemset(n->grads, 0, P);
     if (e == hipSuccess) e = hipMemset(n->m, 0, P);
     if (e == hipSuccess) e = hipMemset(n->v, 0, P);
     if (e == hipSuccess) e = hipMemcpy(n->mean, mean.data(), 16 * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(n->inv_std, one.data(), 16 * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(n->std_dev, one.data(), 16 * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(n->out_std, one.data(), 32 * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(n->inv_out_std, one.data(), 32 * sizeof(float), hipMemcpyHostToDevice);
     if (e != hipSuccess) rc = nn_hip(e, "lbm_nn_create: initialise");
   }
   if (rc == LBM_OK) rc = nn_pack_weights(n);
@@ -433,7 +434,7 @@ int lbm_nn_destroy(lbm_nn n) {
   (void)nn_select(n);
   if (n->stream) (void)hipStreamSynchronize(n->stream);
   for (void* p : {(void*)n->params, (void*)n->grads, (void*)n->m, (void*)n->v, (void*)n->mean, (void*)n->inv_std,
-                  (void*)n->std_dev, (void*)n->dA, (void*)n->dB, (void*)n->y, (void*)n->part, (void*)n->lpart,
+                  (void*)n->out_std, (void*)n->inv_out_std, (void*)n->dA, (void*)n->dB, (void*)n->y, (void*)n->part, (void*)n->lpart,
                   (void*)n->fld, (void*)n->dfld})
     if (p) (void)hipFree(p);
   for (__bf16* p : n->act)
@@ -490,22 +491,29 @@ int lbm_nn_zero_grad(lbm_nn n) {
   return LBM_OK;
 }
 
-int lbm_nn_set_scaling(lbm_nn n, const double* mean, const double* sd) {
+int lbm_nn_set_scaling(lbm_nn n, const double* mean, const double* sd, const double* out_sd) {
   if (!n || !mean || !sd) return nn_fail(LBM_EINVAL, "lbm_nn_set_scaling: NULL argument");
-  std::vector<float> m(16, 0.f), is(16, 1.f), s(16, 1.f);
+  std::vector<float> m(16, 0.f), is(16, 1.f), os(32, 1.f), ios(32, 1.f);
   for (int c = 0; c < n->ch[0]; ++c) {
     if (!(sd[c] > 0.0) || !std::isfinite(sd[c]) || !std::isfinite(mean[c]))
       return nn_fail(LBM_EINVAL, "lbm_nn_set_scaling: std must be finite and > 0");
     m[c] = (float)mean[c];
-    s[c] = (float)sd[c];
     is[c] = (float)(1.0 / sd[c]);
-    n->std_host[c] = sd[c];
+  }
+  const double* o = out_sd ? out_sd : sd;
+  for (int c = 0; c < n->ch[n->L]; ++c) {
+    if (!(o[c] > 0.0) || !std::isfinite(o[c]))
+      return nn_fail(LBM_EINVAL, "lbm_nn_set_scaling: out_std must be finite and > 0");
+    os[c] = (float)o[c];
+    ios[c] = (float)(1.0 / o[c]);
   }
   int rc = nn_select(n);
   if (rc) return rc;
   NN_HIP(hipMemcpyAsync(n->mean, m.data(), 16 * sizeof(float), hipMemcpyHostToDevice, n->stream), "copy mean");
   NN_HIP(hipMemcpyAsync(n->inv_std, is.data(), 16 * sizeof(float), hipMemcpyHostToDevice, n->stream), "copy std");
-  NN_HIP(hipMemcpyAsync(n->std_dev, s.data(), 16 * sizeof(float), hipMemcpyHostToDevice, n->stream), "copy std");
+  NN_HIP(hipMemcpyAsync(n->out_std, os.data(), 32 * sizeof(float), hipMemcpyHostToDevice, n->stream), "copy out_std");
+  NN_HIP(hipMemcpyAsync(n->inv_out_std, ios.data(), 32 * sizeof(float), hipMemcpyHostToDevice, n->stream),
+         "copy out_std");
   NN_HIP(hipStreamSynchronize(n->stream), "hipStreamSynchronize");
   return LBM_OK;
 }
@@ -528,7 +536,7 @@ int lbm_nn_loss_backward(lbm_nn n, const float* x, const float* target, double* 
   if ((rc = nn_forward(n, x))) return rc;
   const int V = n->V, C = n->ch[n->L];
   const int lblocks = (V + 255) / 256;
-  hipLaunchKernelGGL(lbmnn::loss_kernel, dim3(lblocks), dim3(256), 0, n->stream, n->y, x, target, n->inv_std, C, V,
+  hipLaunchKernelGGL(lbmnn::loss_kernel, dim3(lblocks), dim3(256), 0, n->stream, n->y, x, target, n->inv_out_std, C, V,
                      n->dA, n->lpart);
   NN_HIP(hipGetLastError(), "loss kernel");
   // dA holds the gradient with respect to the output of layer l (pre-ReLU for l < L-1)
@@ -585,6 +593,18 @@ int lbm_nn_adam_step(lbm_nn n, double lr, double beta1, double beta2, double eps
   return nn_pack_weights(n);
 }
 
+int lbm_nn_fields_to_planes(int D, int64_t nodes, const double* rho, const double* u, const double* T, float* x,
+                            void* stream) {
+  if (!rho || !u || !T || !x) return nn_fail(LBM_EINVAL, "lbm_nn_fields_to_planes: NULL argument");
+  if ((D != 2 && D != 3) || nodes < 1 || nodes > (1LL << 31) - 256)
+    return nn_fail(LBM_EINVAL, "lbm_nn_fields_to_planes: bad lattice or node count");
+  const int V = (int)nodes;
+  hipLaunchKernelGGL(lbmnn::fields_to_input_kernel, dim3((V + 255) / 256), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), rho, u, T, D, V, x);
+  NN_HIP(hipGetLastError(), "fields kernel");
+  return LBM_OK;
+}
+
 int lbm_nn_correct(lbm_nn n, lbm_handle h) {
   if (!n || !h) return nn_fail(LBM_EINVAL, "lbm_nn_correct: NULL argument");
   const int D = h->lattice;
@@ -612,7 +632,7 @@ int lbm_nn_correct(lbm_nn n, lbm_handle h) {
     if (rc == LBM_OK) rc = nn_forward(n, n->fld);
     if (rc == LBM_OK) {
       hipLaunchKernelGGL(lbmnn::output_to_increments_kernel, dim3((V + 255) / 256), dim3(256), 0, n->stream, n->y,
-                         n->std_dev, D, V, drho, du, dT);
+                         n->out_std, D, V, drho, du, dT);
       e = hipGetLastError();
       if (e != hipSuccess) rc = nn_hip(e, "increments kernel");
     }

@@ -12,6 +12,14 @@ import os
 
 import numpy as np
 
+try:
+    # torch ships its own HIP runtime; loading it before liblbm.so lets the
+    # library bind to that same runtime, so the process has one runtime and
+    # torch's device memory and streams are valid in the library's calls.
+    import torch  # noqa: F401
+except ImportError:  # host-only use (symbol checks) needs no torch
+    pass
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
@@ -84,11 +92,13 @@ def _load():
     L.lbm_nn_get_params.argtypes = [vp, vp, C.c_int]
     L.lbm_nn_get_grads.argtypes = [vp, vp, C.c_int]
     L.lbm_nn_zero_grad.argtypes = [vp]
-    L.lbm_nn_set_scaling.argtypes = [vp, dp, dp]
+    L.lbm_nn_set_scaling.argtypes = [vp, dp, dp, dp]
     L.lbm_nn_forward.argtypes = [vp, vp, vp]
     L.lbm_nn_loss_backward.argtypes = [vp, vp, vp, dp]
     L.lbm_nn_adam_step.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, i64]
     L.lbm_nn_correct.argtypes = [vp, vp]
+    L.lbm_nn_fields_to_planes.argtypes = [C.c_int, i64, vp, vp, vp, vp, vp]
+    L.lbm_fields_set.argtypes = [vp, vp, vp, vp, C.c_int]
     L.lbm_batch_create.argtypes = [C.POINTER(vp), C.POINTER(vp), C.c_int]
     L.lbm_batch_destroy.argtypes = [vp]
     L.lbm_batch_set_stream.argtypes = [vp, vp]
@@ -102,7 +112,7 @@ def _load():
                  "lbm_batch_tune", "lbm_batch_step", "lbm_fields_add", "lbm_filter_moments", "lbm_nn_create",
                  "lbm_nn_destroy", "lbm_nn_set_stream", "lbm_nn_set_params", "lbm_nn_get_params", "lbm_nn_get_grads",
                  "lbm_nn_zero_grad", "lbm_nn_set_scaling", "lbm_nn_forward", "lbm_nn_loss_backward",
-                 "lbm_nn_adam_step", "lbm_nn_correct"):
+                 "lbm_nn_adam_step", "lbm_nn_correct", "lbm_nn_fields_to_planes", "lbm_fields_set"):
         getattr(L, name).restype = C.c_int
     return L
 
@@ -319,6 +329,13 @@ def lbm_fields_add(h, drho, du, dT) -> int:
     return _check(_L.lbm_fields_add(h, pr, pu, pt, _same_kind(kr, ku, kt)))
 
 
+def lbm_fields_set(h, rho, u, T) -> int:
+    pr, kr, _a = _arg(rho)
+    pu, ku, _b = _arg(u)
+    pt, kt, _c = _arg(T)
+    return _check(_L.lbm_fields_set(h, pr, pu, pt, _same_kind(kr, ku, kt)))
+
+
 def lbm_filter_moments(h, factor, rho, u, T):
     """Writes the coarse moments into rho, u, T (numpy arrays or device tensors)."""
     args = [_arg(x) for x in (rho, u, T)]
@@ -378,11 +395,13 @@ def lbm_nn_zero_grad(n) -> int:
     return _check(_L.lbm_nn_zero_grad(n))
 
 
-def lbm_nn_set_scaling(n, mean, std) -> int:
+def lbm_nn_set_scaling(n, mean, std, out_std=None) -> int:
     m = np.ascontiguousarray(mean, dtype=np.float64)
     s = np.ascontiguousarray(std, dtype=np.float64)
-    return _check(_L.lbm_nn_set_scaling(n, m.ctypes.data_as(C.POINTER(C.c_double)),
-                                        s.ctypes.data_as(C.POINTER(C.c_double))))
+    o = None if out_std is None else np.ascontiguousarray(out_std, dtype=np.float64)
+    dp = C.POINTER(C.c_double)
+    return _check(_L.lbm_nn_set_scaling(n, m.ctypes.data_as(dp), s.ctypes.data_as(dp),
+                                        None if o is None else o.ctypes.data_as(dp)))
 
 
 def lbm_nn_forward(n, x, y) -> int:
@@ -406,6 +425,20 @@ def lbm_nn_loss_backward(n, x, target) -> float:
 
 def lbm_nn_adam_step(n, lr, beta1=0.9, beta2=0.999, eps=1e-8, grad_scale=1.0, t=1) -> int:
     return _check(_L.lbm_nn_adam_step(n, float(lr), float(beta1), float(beta2), float(eps), float(grad_scale), int(t)))
+
+
+def lbm_nn_fields_to_planes(D, rho, u, T, x, stream=None) -> int:
+    """Device FP64 fields -> the FP32 planes x (device tensor of D + 2 planes)."""
+    args = [_arg(a) for a in (rho, u, T)]
+    px, kx, _k = _arg(x, dtype=np.float32)
+    if any(a[1] != LBM_DEVICE for a in args) or kx != LBM_DEVICE:
+        raise ValueError("lbm_nn_fields_to_planes takes device tensors")
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    nodes = rho.numel()
+    if x.numel() < (D + 2) * nodes or u.numel() < D * nodes or T.numel() < nodes:
+        raise ValueError("lbm_nn_fields_to_planes: arrays too small")
+    return _check(_L.lbm_nn_fields_to_planes(int(D), int(nodes), args[0][0], args[1][0], args[2][0], px, stream))
 
 
 def lbm_nn_correct(n, h) -> int:

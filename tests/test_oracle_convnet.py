@@ -98,3 +98,39 @@ def test_spectrum_parseval_and_single_mode():
     w[1] = np.cos(2 * np.pi * 3 * x / 8)  # one mode at |k| = 3
     E = N.kinetic_energy_spectrum(w)
     assert E[3] == pytest.approx(0.25, rel=1e-12) and E.sum() == pytest.approx(0.25, rel=1e-12)
+
+
+def test_bf16_rounding_follows_the_format():
+    """bfloat16 keeps 8 significant bits: representable values pass unchanged,
+    halfway cases go to the even neighbour, and the relative error of any
+    normal value is at most 2^-8 (half a unit in the 8th significant bit)."""
+    for v in (0.0, 1.0, 1.5, -2.0, 2.0 ** -100, 3.0 * 2.0 ** 60, 1.0 + 2.0 ** -7):
+        assert N.bf16(v) == v
+    assert N.bf16(1.0 + 2.0 ** -8) == 1.0  # tie, 1.0 is even
+    assert N.bf16(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6  # tie, 1 + 2^-7 is odd
+    assert N.bf16(1.0 + 2.0 ** -8 + 2.0 ** -20) == 1.0 + 2.0 ** -7  # above the tie
+    assert N.bf16(-(1.0 + 2.0 ** -8 + 2.0 ** -20)) == -(1.0 + 2.0 ** -7)
+    x = np.random.default_rng(8).normal(size=10000) * 10.0 ** np.random.default_rng(9).integers(-20, 20, 10000)
+    r = N.bf16(x)
+    assert np.all(np.abs(r - x) <= (2.0 ** -8 + 2.0 ** -24) * np.abs(x))  # FP32 first, then bf16
+    assert np.all(N.bf16(r) == r)
+
+
+def test_bf16_storage_changes_the_network_by_its_rounding_only():
+    """With bf16 storage the loss stays within a few roundings of FP64 and the
+    gradients keep their direction; with representable operands and a single
+    linear layer (no stored activations) nothing changes at all."""
+    ch = [3, 32, 32, 3]
+    p = _rand_params(ch, 10, scale=0.15)
+    r = np.random.default_rng(11)
+    x = 1.0 + 0.1 * r.normal(size=(3, 4, 4, 8))
+    t = x + 0.05 * r.normal(size=x.shape)
+    mean, std = np.array([1.0, 1.0, 1.0]), np.array([0.1, 0.1, 0.1])
+    l64, g64 = N.loss_and_grad(p, ch, x, t, mean, std)
+    l16, g16 = N.loss_and_grad(p, ch, x, t, mean, std, store=N.bf16)
+    assert l16 == pytest.approx(l64, rel=2e-2) and l16 != l64
+    assert g16 @ g64 / (np.linalg.norm(g16) * np.linalg.norm(g64)) > 0.99
+    one = [2, 3]
+    q = N.bf16(_rand_params(one, 12))
+    xi = N.bf16(r.normal(size=(2, 3, 4, 5)))
+    assert np.array_equal(N.forward(q, one, xi, store=N.bf16)[0], N.forward(q, one, xi)[0])
