@@ -11,7 +11,7 @@
  *   y[v][o] = b[o] + sum_{t < 27} sum_{i} x[v + s_t][i] W[t][i][o]
  * with s_t = (t%3 - 1, (t/3)%3 - 1, t/9 - 1) (x, y, z offsets, periodic wrap)
  * and a ReLU after every layer but the last.  Supported: c[0] <= 16, hidden
- * widths exactly 32, c[L] <= 32; nx*ny*nz a multiple of 256.
+ * widths exactly 32, c[L] <= 32; nx a multiple of 32, ny and nz multiples of 4.
  *
  * Tensors at the ABI are FP32 and planar: x[c][z][y][x] (node = x + nx*(y +
  * ny*z), the node order of lbm.h), on the device (LBM_DEVICE) unless stated.

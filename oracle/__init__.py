@@ -50,7 +50,7 @@ class _Params(C.Structure):
     _fields_ = [
         ("D", C.c_int), ("n", C.c_long * 3), ("bc", C.c_int * 3), ("gamma", C.c_double),
         ("Pr", C.c_double), ("mu0", C.c_double), ("visc_exp", C.c_double),
-        ("T_ref", C.c_double), ("deriv", C.c_int),
+        ("T_ref", C.c_double), ("deriv", C.c_int), ("cv", C.c_double * 3),
     ]
 
 
@@ -82,6 +82,12 @@ def lib():
         L.orc_feq.argtypes = [C.c_int, C.c_double, _dp, C.c_double, _dp]
         L.orc_fex.argtypes = [C.c_int, C.c_double, _dp, C.c_double, C.c_double, _dp, _dp]
         L.orc_geq.argtypes = [C.c_int, C.c_double, _dp, C.c_double, C.c_double, _dp]
+        L.orc_geq_u.argtypes = [C.c_int, C.c_double, _dp, C.c_double, C.c_double, _dp]
+        L.orc_caloric.argtypes = [C.POINTER(_Params), _dp]
+        L.orc_internal_energy.argtypes = [_dp, C.c_double]
+        L.orc_internal_energy.restype = C.c_double
+        L.orc_temperature.argtypes = [_dp, C.c_double]
+        L.orc_temperature.restype = C.c_double
         L.orc_dq.argtypes = [C.c_int, C.c_double, _dp, C.c_double, _dp, _dp, _dp]
         L.orc_gstar.argtypes = [C.c_int, C.c_double, _dp, C.c_double, C.c_double, _dp, _dp, _dp]
         for name in ("orc_anomaly",):
@@ -126,14 +132,33 @@ def velocities(D: int) -> np.ndarray:
 
 
 def make_params(D, dims, gamma=1.4, Pr=0.71, mu=0.01, visc_exp=0.0, T_ref=1.0,
-                bc=(PERIODIC, PERIODIC, PERIODIC), deriv=UPWIND) -> _Params:
+                bc=(PERIODIC, PERIODIC, PERIODIC), deriv=UPWIND, cv=None) -> _Params:
+    """cv: (c0, c1, c2) of C_v(T) = c0 + c1 T + c2 T^2, or None for 1/(gamma-1)."""
     p = _Params()
     p.D = D
     for a in range(3):
         p.n[a] = int(dims[a]) if a < len(dims) else 1
         p.bc[a] = int(bc[a])
     p.gamma, p.Pr, p.mu0, p.visc_exp, p.T_ref, p.deriv = gamma, Pr, mu, visc_exp, T_ref, deriv
+    for k in range(3):
+        p.cv[k] = float(cv[k]) if cv is not None else 0.0
     return p
+
+
+def caloric(cv=None, gamma=1.4) -> np.ndarray:
+    """The C_v(T) coefficients in effect (orc_caloric)."""
+    p = make_params(3, (1, 1, 1), gamma=gamma, cv=cv)
+    out = np.zeros(3)
+    lib().orc_caloric(C.byref(p), _ptr(out))
+    return out
+
+
+def internal_energy(cv, T) -> float:
+    return lib().orc_internal_energy(_ptr(np.ascontiguousarray(cv, dtype=np.float64)), float(T))
+
+
+def temperature(cv, e) -> float:
+    return lib().orc_temperature(_ptr(np.ascontiguousarray(cv, dtype=np.float64)), float(e))
 
 
 # ---- nodal functions -------------------------------------------------------
@@ -159,6 +184,13 @@ def fex(D, rho, u, T, omega, d):
 def geq(D, rho, u, T, Cv):
     out = np.zeros(Q(D))
     lib().orc_geq(D, rho, _ptr(_vec(u)), T, Cv, _ptr(out))
+    return out
+
+
+def geq_u(D, rho, u, T, U):
+    """g^eq with the internal energy U = U(T) of any caloric law."""
+    out = np.zeros(Q(D))
+    lib().orc_geq_u(D, rho, _ptr(_vec(u)), T, U, _ptr(out))
     return out
 
 
@@ -203,10 +235,10 @@ class Sim:
     """Whole-field oracle simulation (see oracle.h)."""
 
     def __init__(self, D, dims, gamma=1.4, Pr=0.71, mu=0.01, visc_exp=0.0, T_ref=1.0,
-                 bc=(PERIODIC, PERIODIC, PERIODIC), deriv=UPWIND):
+                 bc=(PERIODIC, PERIODIC, PERIODIC), deriv=UPWIND, cv=None):
         dims = tuple(int(d) for d in dims) + (1,) * (3 - len(dims))
         self.D, self.dims = D, dims
-        self.params = make_params(D, dims, gamma, Pr, mu, visc_exp, T_ref, bc, deriv)
+        self.params = make_params(D, dims, gamma, Pr, mu, visc_exp, T_ref, bc, deriv, cv)
         self._h = lib().orc_create(C.byref(self.params))
         if not self._h:
             raise ValueError("oracle: invalid parameters")

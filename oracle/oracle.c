@@ -47,7 +47,7 @@ struct orc_sim {
   orc_params p;
   long N;
   int Q;
-  double Cv;
+  double cv[3]; /* caloric law in effect */
   long step;
   double* f;  /* [Q][N] post-collision populations */
   double* g;
@@ -158,12 +158,12 @@ static poly apply_psi_op(int c, const poly* A, double T) {
 }
 
 /* g^eq_i = rho prod_a Psi_{c_ia}(O_a, O_a^2) E, Eq. (42), with the generating
-   function E = C_v T + |u|^2 / 2 (Eqs. (6)-(7), constant C_v, T_ref = 0).
+   function E = U(T) + |u|^2 / 2 (Eqs. (6)-(7), T_ref = 0).
    E is a sum of terms that factor over the velocity components,
-     E = (C_v T) * 1 * 1 * 1 + sum_a (u_a^2 / 2) * prod_{b != a} 1,
-   and O_a acts on the u_a factor only, so each term is transformed factor by
-   factor with the one-variable operator above. */
-void orc_geq(int D, double rho, const double* u, double T, double Cv, double* g) {
+     E = U * 1 * 1 * 1 + sum_a (u_a^2 / 2) * prod_{b != a} 1,
+   U does not depend on u, and O_a acts on the u_a factor only, so each term
+   is transformed factor by factor with the one-variable operator above. */
+void orc_geq_u(int D, double rho, const double* u, double T, double U, double* g) {
   int Q = orc_Q(D);
   poly one, sq;
   memset(&one, 0, sizeof one);
@@ -182,7 +182,7 @@ void orc_geq(int D, double rho, const double* u, double T, double Cv, double* g)
   for (int i = 0; i < Q; ++i) {
     int c[3];
     orc_velocity(D, i, c);
-    double s = Cv * T;
+    double s = U;
     for (int a = 0; a < D; ++a) s *= t_one[a][c[a] + 1];
     for (int a = 0; a < D; ++a) {
       double t = 0.5 * t_sq[a][c[a] + 1];
@@ -192,6 +192,44 @@ void orc_geq(int D, double rho, const double* u, double T, double Cv, double* g)
     }
     g[i] = rho * s;
   }
+}
+
+/* Constant C_v: U = C_v T. */
+void orc_geq(int D, double rho, const double* u, double T, double Cv, double* g) {
+  orc_geq_u(D, rho, u, T, Cv * T, g);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Caloric law, Eq. (6): U(T) = integral of C_v from 0 to T                  */
+/* ------------------------------------------------------------------------ */
+
+void orc_caloric(const orc_params* p, double cv[3]) {
+  if (p->cv[0] == 0.0 && p->cv[1] == 0.0 && p->cv[2] == 0.0) {
+    cv[0] = 1.0 / (p->gamma - 1.0);
+    cv[1] = cv[2] = 0.0;
+  } else {
+    for (int k = 0; k < 3; ++k) cv[k] = p->cv[k];
+  }
+}
+
+double orc_internal_energy(const double* cv, double T) {
+  return cv[0] * T + cv[1] * T * T / 2.0 + cv[2] * T * T * T / 3.0;
+}
+
+static double specific_heat(const double* cv, double T) { return cv[0] + cv[1] * T + cv[2] * T * T; }
+
+/* Newton's method on U(T) = e, started from the constant-C_v guess e / cv[0];
+   U is increasing (C_v > 0), and convex for cv[1], cv[2] >= 0, so the
+   iterates approach the root monotonically after the first step. */
+double orc_temperature(const double* cv, double e) {
+  double T = e / cv[0];
+  if (cv[1] == 0.0 && cv[2] == 0.0) return T;
+  for (int it = 0; it < 100; ++it) {
+    double dT = (orc_internal_energy(cv, T) - e) / specific_heat(cv, T);
+    T -= dT;
+    if (fabs(dT) <= 1e-16 * fabs(T)) break;
+  }
+  return T;
 }
 
 /* q* - q^eq = u . (P - P^eq + (delta_t/2) div Qt), Eq. (46).  Only the
@@ -257,8 +295,8 @@ typedef struct {
 } node_state;
 
 /* rho = sum f, rho u = sum c f (Eqs. (3)-(4)), P = sum c c f (Eq. (47)),
-   rho E = sum g (Eq. (5)), T from E = C_v T + u^2/2 (Eqs. (6)-(7)). */
-static void node_moments(int D, const double* f, const double* g, double Cv, node_state* m) {
+   rho E = sum g (Eq. (5)), T from E = U(T) + u^2/2 (Eqs. (6)-(7)). */
+static void node_moments(int D, const double* f, const double* g, const double* cv, node_state* m) {
   int Q = orc_Q(D);
   double rho = 0.0, j[3] = {0, 0, 0}, P[9] = {0}, rhoE = 0.0;
   for (int i = 0; i < Q; ++i) {
@@ -280,7 +318,7 @@ static void node_moments(int D, const double* f, const double* g, double Cv, nod
   }
   for (int k = 0; k < 9; ++k) m->P[k] = P[k];
   double E = rhoE / rho;
-  m->T = (E - 0.5 * u2) / Cv;
+  m->T = orc_temperature(cv, E - 0.5 * u2);
 }
 
 static void node_relax_rates(const orc_params* p, node_state* m) {
@@ -290,12 +328,12 @@ static void node_relax_rates(const orc_params* p, node_state* m) {
 
 /* f_i <- fh_i + omega (f^ex_i - fh_i), Eq. (1);
    g_i <- gh_i + omega_1 (g^eq_i - gh_i) + (omega - omega_1)(g^eq_i - g*_i), Eq. (2). */
-static void node_collide(int D, double Cv, const node_state* m, const double* fh, const double* gh,
+static void node_collide(int D, const double* cv, const node_state* m, const double* fh, const double* gh,
                          const double* d, double* f_out, double* g_out) {
   int Q = orc_Q(D);
   double fex[QMAX], geq[QMAX], gst[QMAX], dq[3];
   orc_fex(D, m->rho, m->u, m->T, m->omega, d, fex);
-  orc_geq(D, m->rho, m->u, m->T, Cv, geq);
+  orc_geq_u(D, m->rho, m->u, m->T, orc_internal_energy(cv, m->T), geq);
   orc_dq(D, m->rho, m->u, m->T, m->P, d, dq);
   quasi_equilibrium(D, geq, dq, gst);
   for (int i = 0; i < Q; ++i) {
@@ -306,11 +344,12 @@ static void node_collide(int D, double Cv, const node_state* m, const double* fh
 
 void orc_collide_node(const orc_params* p, const double* fh, const double* gh, const double* d,
                       double* f_out, double* g_out) {
-  double Cv = 1.0 / (p->gamma - 1.0);
+  double cv[3];
+  orc_caloric(p, cv);
   node_state m;
-  node_moments(p->D, fh, gh, Cv, &m);
+  node_moments(p->D, fh, gh, cv, &m);
   node_relax_rates(p, &m);
-  node_collide(p->D, Cv, &m, fh, gh, d, f_out, g_out);
+  node_collide(p->D, cv, &m, fh, gh, d, f_out, g_out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -360,12 +399,16 @@ orc_sim* orc_create(const orc_params* p) {
   for (int a = 0; a < 3; ++a)
     if (p->bc[a] != ORC_PERIODIC && p->bc[a] != ORC_ZERO_GRADIENT) return NULL;
   if (p->deriv != ORC_UPWIND && p->deriv != ORC_CENTRAL) return NULL;
+  /* a caloric law, when given, needs C_v > 0 and U convex: c0 > 0, c1, c2 >= 0 */
+  if ((p->cv[0] != 0.0 || p->cv[1] != 0.0 || p->cv[2] != 0.0) &&
+      !(p->cv[0] > 0.0 && p->cv[1] >= 0.0 && p->cv[2] >= 0.0))
+    return NULL;
   orc_sim* s = (orc_sim*)calloc(1, sizeof *s);
   if (!s) return NULL;
   s->p = *p;
   s->N = p->n[0] * p->n[1] * p->n[2];
   s->Q = orc_Q(p->D);
-  s->Cv = 1.0 / (p->gamma - 1.0);
+  orc_caloric(p, s->cv);
   size_t NQ = (size_t)s->N * (size_t)s->Q;
   size_t ND = (size_t)s->N * (size_t)p->D;
   s->f = (double*)malloc(NQ * sizeof(double));
@@ -414,7 +457,7 @@ int orc_init(orc_sim* s, const double* rho, const double* u, const double* T) {
     double un[3] = {0, 0, 0}, fe[QMAX], ge[QMAX];
     for (int a = 0; a < D; ++a) un[a] = u[a * N + n];
     orc_feq(D, rho[n], un, T[n], fe);
-    orc_geq(D, rho[n], un, T[n], s->Cv, ge);
+    orc_geq_u(D, rho[n], un, T[n], orc_internal_energy(s->cv, T[n]), ge);
     for (int i = 0; i < s->Q; ++i) {
       s->f[(size_t)i * N + n] = fe[i];
       s->g[(size_t)i * N + n] = ge[i];
@@ -468,7 +511,7 @@ static void pass1_node(orc_sim* s, long n) {
     s->gh[(size_t)i * N + n] = gl[i];
   }
   node_state m;
-  node_moments(D, fl, gl, s->Cv, &m);
+  node_moments(D, fl, gl, s->cv, &m);
   s->rho[n] = m.rho;
   s->T[n] = m.T;
   for (int a = 0; a < D; ++a) {
@@ -488,10 +531,10 @@ static void pass2_node(const orc_sim* s, long n, double* f_out, long f_stride, d
     gl[i] = s->gh[(size_t)i * N + n];
   }
   node_state m;
-  node_moments(D, fl, gl, s->Cv, &m);
+  node_moments(D, fl, gl, s->cv, &m);
   node_relax_rates(p, &m);
   for (int a = 0; a < D; ++a) d[a] = s->dd[(size_t)a * N + n];
-  node_collide(D, s->Cv, &m, fl, gl, d, fo, go);
+  node_collide(D, s->cv, &m, fl, gl, d, fo, go);
   for (int i = 0; i < Q; ++i) {
     f_out[(size_t)i * f_stride] = fo[i];
     g_out[(size_t)i * g_stride] = go[i];
@@ -555,7 +598,7 @@ int orc_moments(const orc_sim* s, double* rho, double* u, double* T) {
       gl[i] = s->g[(size_t)i * N + n];
     }
     node_state m;
-    node_moments(D, fl, gl, s->Cv, &m);
+    node_moments(D, fl, gl, s->cv, &m);
     if (rho) rho[n] = m.rho;
     if (T) T[n] = m.T;
     if (u)
@@ -625,7 +668,13 @@ int orc_diagnostics(const orc_sim* s, double* out) {
     c[(size_t)ORC_D_KINETIC * N] = 0.5 * rho[n] * uu;
     c[(size_t)ORC_D_DIL2 * N] = div * div;
     c[(size_t)ORC_D_U2 * N] = uu;
-    c[(size_t)ORC_D_CS * N] = sqrt(p->gamma * T[n]);
+    /* sound speed sqrt(gamma(T) T), gamma = C_p / C_v = (C_v + 1) / C_v, Eq. (97) */
+    double gam = p->gamma;
+    if (s->cv[1] != 0.0 || s->cv[2] != 0.0) {
+      double cvT = specific_heat(s->cv, T[n]);
+      gam = (cvT + 1.0) / cvT;
+    }
+    c[(size_t)ORC_D_CS * N] = sqrt(gam * T[n]);
     c[(size_t)ORC_D_RHO2 * N] = rho[n] * rho[n];
     c[(size_t)ORC_D_VORT2 * N] = vort2;
     c[(size_t)ORC_D_DISS * N] = viscosity(p, T[n]) * vort2;

@@ -8,8 +8,10 @@
  * CPU-baseline leg of the benchmark may load it.  It shares no source, header
  * or generated table with the GPU library, and the GPU library never calls it.
  *
- * Lattice units throughout: delta_t = delta_x = 1 and R = 1 (Sec. III.A);
- * constant specific heats C_v = 1/(gamma-1), C_p = gamma/(gamma-1).
+ * Lattice units throughout: delta_t = delta_x = 1 and R = 1 (Sec. III.A).
+ * Caloric law (Sec. II.A, Eq. (6)): C_v(T) = cv[0] + cv[1] T + cv[2] T^2, so
+ * U(T) = cv[0] T + cv[1] T^2/2 + cv[2] T^3/3 and C_p = C_v + 1 (Mayer);
+ * cv all zero selects the constant C_v = 1/(gamma-1) of the paper's runs.
  *
  * Velocity numbering (the paper fixes none): c_i = (i%3-1, (i/3)%3-1, (i/9)%3-1)
  * with Q = 3^D; for D = 2 the z component is dropped (Q = 9).
@@ -37,6 +39,7 @@ typedef struct {
   double visc_exp;  /* mu = mu0 (T/T_ref)^visc_exp  (Sec. III.D); 0 = constant mu */
   double T_ref;     /* reference temperature of the power law */
   int deriv;        /* ORC_UPWIND (Sec. III.A) or ORC_CENTRAL (Sec. III.D.2) */
+  double cv[3];     /* C_v(T) coefficients (see above); all zero = 1/(gamma-1) */
 } orc_params;
 
 /* Diagnostic slots written by orc_diagnostics (all FP64 sums over nodes). */
@@ -58,6 +61,12 @@ enum {
   ORC_D_NODES,        /* node count */
   ORC_NDIAG
 };
+
+/* Caloric law: the coefficients in effect for p (cv, or 1/(gamma-1) when cv
+   is all zero); U(T) (Eq. (6)); T from U by Newton's method on U(T) = e. */
+void orc_caloric(const orc_params* p, double cv[3]);
+double orc_internal_energy(const double* cv, double T);
+double orc_temperature(const double* cv, double e);
 
 typedef struct orc_sim orc_sim;
 
@@ -91,6 +100,8 @@ void orc_feq(int D, double rho, const double* u, double T, double* f);
 void orc_fex(int D, double rho, const double* u, double T, double omega, const double* d, double* f);
 /* g^eq by operator product form, Eq. (42), with E of Eq. (7) at constant C_v. */
 void orc_geq(int D, double rho, const double* u, double T, double Cv, double* g);
+/* The same with the internal energy U = U(T) of any caloric law given. */
+void orc_geq_u(int D, double rho, const double* u, double T, double U, double* g);
 /* q* - q^eq, Eq. (46); P is the D x D pressure tensor of the populations (row-major). */
 void orc_dq(int D, double rho, const double* u, double T, const double* P, const double* d, double* dq);
 /* g*, Eq. (44). */

@@ -59,43 +59,103 @@ __global__ void __launch_bounds__(256) pack_input_kernel(const float* __restrict
   *(bf8*)(a + (size_t)v * 16 + 8) = hi;
 }
 
-// out[v][o] = bias[o] + sum_t sum_i in[shift(v, t)][i] w[t][i][o]  (cross-correlation)
-// CIN: channels of in (16 or 32).  OUT_PLANAR: write FP32 planes out[o][v] for
-// o < cout, else bf16 out[v][32].  relu: max(., 0).  mask (bf16 [v][32], may
-// be null): zero where mask <= 0 (the derivative of the ReLU that produced it).
+// Output tile of the convolution kernel: 32 nodes along x (the matrix-core
+// N dimension) times 4 rows along y times 4 planes along z; wave w computes
+// plane z0 + w.  The input tile with its one-node periodic halo is staged in
+// LDS once per block and read 27 times.
+constexpr int kTX = 32, kTY = 4, kTZ = 4;
+constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
+
+// 16-byte chunk c of the node at halo column hx is stored at chunk
+// c ^ f(hx): eight consecutive lanes (consecutive hx, same c) then read eight
+// disjoint groups of four banks.
+template <int CIN>
+__device__ inline int swizzle(int c, int hx) {
+  return CIN == 32 ? (c ^ ((hx >> 1) & 3)) : (c ^ ((hx >> 2) & 1));
+}
+
+// out[v][o] = bias[o] + sum_t sum_i in[v + s_t][i] w[t][i][o]  (cross-correlation)
+// as the product W^T (32 outputs x K) times the input columns (K x 32 nodes),
+// K = 27 taps x CIN: A[m = o][k = i] from wp, B[k = i][n = node] from LDS;
+// accumulator i of lane l holds output channel 8(i/4) + 4(l/32) + i%4 of node
+// x0 + l%32.  CIN: channels of in (16 or 32).  OUT_PLANAR: FP32 planes
+// out[o][v] for o < cout, else bf16 out[v][32].  relu: max(., 0).  mask (bf16
+// [v][32], may be null): zero where mask <= 0 (the derivative of the ReLU that
+// produced it).  bias may be null; it holds cout values.
+// Requires nx % 32 == 0, ny % 4 == 0, nz % 4 == 0; grid = tiles.
 template <int CIN, bool OUT_PLANAR>
 __global__ void __launch_bounds__(256) conv_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ wp,
                                                    const float* __restrict__ bias, int relu,
                                                    const __bf16* __restrict__ mask, void* __restrict__ out, int cout,
                                                    const Grid g, int V) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int v0 = (blockIdx.x * 4 + wave) * 32;
-  if (v0 >= V) return;
+  constexpr int CH = CIN / 8;  // 16-byte chunks per node
+  __shared__ __attribute__((aligned(16))) __bf16 tile[kHZ * kHY * kHX * CIN];
+  const int tx = g.nx / kTX, ty = g.ny / kTY;
+  const int b = blockIdx.x;
+  const int x0 = (b % tx) * kTX, y0 = ((b / tx) % ty) * kTY, z0 = (b / (tx * ty)) * kTZ;
+  for (int e = threadIdx.x; e < kHZ * kHY * kHX * CH; e += 256) {
+    const int c = e % CH, node = e / CH;
+    const int hx = node % kHX, hy = (node / kHX) % kHY, hz = node / (kHX * kHY);
+    const int gx = wrap(x0 + hx - 1, g.nx), gy = wrap(y0 + hy - 1, g.ny), gz = wrap(z0 + hz - 1, g.nz);
+    const bf8 val = *(const bf8*)(in + (size_t)(gx + g.nx * (gy + g.ny * gz)) * CIN + c * 8);
+    *(bf8*)(tile + node * CIN + swizzle<CIN>(c, hx) * 8) = val;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r = lane & 31, half = lane >> 5;
-  const int vm = v0 + r;
-  f16v acc = {};
+  f16v acc[kTY] = {};
 #pragma unroll 1
   for (int t = 0; t < 27; ++t) {
-    const __bf16* src = in + (size_t)shifted(vm, t, g) * CIN + 8 * half;
-    const __bf16* wt = wp + ((size_t)t * (CIN / 16) * 32 + r) * 16 + 8 * half;
+    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+    const int hx = r + dx + 1;
+    const __bf16* row0 = tile + ((w + dz + 1) * kHY + dy + 1) * kHX * CIN + hx * CIN;
 #pragma unroll
     for (int cc = 0; cc < CIN / 16; ++cc) {
-      const bf8 a = *(const bf8*)(src + cc * 16);
-      const bf8 b = *(const bf8*)(wt + (size_t)cc * 32 * 16);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      const bf8 a = *(const bf8*)(wp + ((size_t)(t * (CIN / 16) + cc) * 32 + r) * 16 + 8 * half);
+      const int off = swizzle<CIN>(2 * cc + half, hx) * 8;
+#pragma unroll
+      for (int j = 0; j < kTY; ++j) {
+        const bf8 bv = *(const bf8*)(row0 + j * kHX * CIN + off);
+        acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[j], 0, 0, 0);
+      }
     }
   }
-  const float bo = bias ? bias[r] : 0.f;
+  float bo[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    const int v = v0 + 8 * (i >> 2) + 4 * half + (i & 3);
-    float y = acc[i] + bo;
-    if (relu) y = y > 0.f ? y : 0.f;
-    if (mask && !((float)mask[(size_t)v * 32 + r] > 0.f)) y = 0.f;
-    if (OUT_PLANAR) {
-      if (r < cout) static_cast<float*>(out)[(size_t)r * V + v] = y;
-    } else {
-      static_cast<__bf16*>(out)[(size_t)v * 32 + r] = (__bf16)y;
+    const int c = 8 * (i >> 2) + 4 * half + (i & 3);
+    bo[i] = bias && c < cout ? bias[c] : 0.f;
+  }
+#pragma unroll
+  for (int j = 0; j < kTY; ++j) {
+    const int v = (x0 + r) + g.nx * ((y0 + j) + g.ny * (z0 + w));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c0 = 8 * q + 4 * half;
+      float y[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        y[k] = acc[j][4 * q + k] + bo[4 * q + k];
+        if (relu) y[k] = y[k] > 0.f ? y[k] : 0.f;
+      }
+      if (mask) {
+        typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+        const bf4 mk = *(const bf4*)(mask + (size_t)v * 32 + c0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (!((float)mk[k] > 0.f)) y[k] = 0.f;
+      }
+      if (OUT_PLANAR) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (c0 + k < cout) static_cast<float*>(out)[(size_t)(c0 + k) * V + v] = y[k];
+      } else {
+        typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+        bf4 o;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o[k] = (__bf16)y[k];
+        *(bf4*)(static_cast<__bf16*>(out) + (size_t)v * 32 + c0) = o;
+      }
     }
   }
 }
@@ -310,7 +370,7 @@ int nn_pack_weights(lbm_nn n) {
 template <int CIN, bool PLANAR>
 hipError_t conv(lbm_nn n, const __bf16* in, const __bf16* w, const float* bias, int relu, const __bf16* mask,
                 void* out, int cout) {
-  const int blocks = (n->V / 32 + 3) / 4;
+  const int blocks = (n->g.nx / lbmnn::kTX) * (n->g.ny / lbmnn::kTY) * (n->g.nz / lbmnn::kTZ);
   hipLaunchKernelGGL((lbmnn::conv_kernel<CIN, PLANAR>), dim3(blocks), dim3(256), 0, n->stream, in, w, bias, relu,
                      mask, out, cout, n->g, n->V);
   return hipGetLastError();
@@ -353,7 +413,8 @@ int lbm_nn_create(lbm_nn* out, int layers, const int* channels, const int64_t di
   for (int a = 0; a < 3; ++a)
     if (dims[a] < 1 || dims[a] > 4096) return nn_fail(LBM_EINVAL, "lbm_nn_create: dims out of range");
   const int64_t V = dims[0] * dims[1] * dims[2];
-  if (V % 256 || V > (1 << 26)) return nn_fail(LBM_EINVAL, "lbm_nn_create: node count must be a multiple of 256 (<= 2^26)");
+  if (dims[0] % lbmnn::kTX || dims[1] % lbmnn::kTY || dims[2] % lbmnn::kTZ || V > (1 << 26))
+    return nn_fail(LBM_EINVAL, "lbm_nn_create: nx must be a multiple of 32, ny and nz of 4 (at most 2^26 nodes)");
   lbm_nn n = new (std::nothrow) lbm_nn_ctx();
   if (!n) return nn_fail(LBM_ENOMEM, "lbm_nn_create: host allocation failed");
   n->L = layers;

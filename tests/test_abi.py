@@ -100,10 +100,11 @@ def test_batch_null_arguments_fail_cleanly(lbm):
 
 
 @pytest.mark.parametrize("channels,dims,needle", [
-    ([5, 32, 5], (8, 8, 2), "multiple of 256"),
-    ([20, 32, 5], (8, 8, 8), "input channels"),
-    ([5, 16, 5], (8, 8, 8), "hidden widths"),
-    ([5, 32, 40], (8, 8, 8), "output channels"),
+    ([5, 32, 5], (16, 8, 8), "multiple of 32"),
+    ([5, 32, 5], (32, 6, 8), "multiple of 32"),
+    ([20, 32, 5], (32, 8, 8), "input channels"),
+    ([5, 16, 5], (32, 8, 8), "hidden widths"),
+    ([5, 32, 40], (32, 8, 8), "output channels"),
 ])
 def test_nn_create_rejects_bad_shapes(lbm, channels, dims, needle):
     with pytest.raises(lbm.LbmError) as e:

@@ -54,7 +54,7 @@ def _rel(a, b):
 
 def test_forward_matches_reference():
     lbm = _lbm()
-    shape = (8, 8, 8)
+    shape = (8, 8, 64)  # z, y, x: two tiles along x, two along y and z
     p = _params(1)
     x = _fields(shape, 2)
     n = lbm.lbm_nn_create(CH, shape[::-1])
@@ -80,7 +80,7 @@ def test_forward_matches_reference():
 
 def test_loss_and_gradients_match_reference():
     lbm = _lbm()
-    shape = (8, 8, 16)
+    shape = (8, 4, 64)
     p = _params(3)
     x = _fields(shape, 4)
     t = x + 0.3 * OUT[:, None, None, None] * np.random.default_rng(5).normal(size=x.shape)
@@ -120,7 +120,7 @@ def test_loss_and_gradients_match_reference():
 
 def test_adam_step_matches_reference():
     lbm = _lbm()
-    shape = (8, 8, 8)
+    shape = (4, 4, 32)
     p = _params(6)
     x = _fields(shape, 7)
     t = x * 1.01
@@ -148,7 +148,7 @@ def test_training_reduces_the_loss():
     """A target that is a fixed smooth function of the input: the network
     learns it (the loss falls tenfold in 150 Adam steps on one sample set)."""
     lbm = _lbm()
-    shape = (8, 8, 16)
+    shape = (4, 8, 32)
     xs, ts = [], []
     for s in range(4):
         rho, u, T = I.smooth_random(3, shape[::-1], seed=30 + s, u_amp=0.1)
@@ -248,7 +248,7 @@ def test_filter_moments_matches_reference(D):
 def test_correct_adds_the_network_output():
     """lbm_nn_correct = moments -> network -> increments out_std * y -> fields_add."""
     lbm = _lbm()
-    dims = (8, 8, 8)
+    dims = (32, 8, 4)
     rho, u, T = I.smooth_random(3, dims, seed=12, u_amp=0.05)
     h = lbm.lbm_create(3, dims, 1.4, 0.7, 0.02, precision=lbm.LBM_FP32_DEV, visc_exponent=0.76, T_ref=0.15)
     n = lbm.lbm_nn_create(CH, dims)

@@ -16,7 +16,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
 PINS = [os.path.join(ROOT, "tests", "test_oracle_equilibria.py"),
-        os.path.join(ROOT, "tests", "test_oracle_physics.py")]
+        os.path.join(ROOT, "tests", "test_oracle_physics.py"),
+        os.path.join(ROOT, "tests", "test_oracle_caloric.py")]
 
 MUTANTS = [
     ("psi_minus_sign", "return 0.5 * (-xi + P);", "return 0.5 * (xi + P);"),
@@ -33,12 +34,16 @@ MUTANTS = [
     ("quasi_eq_sign", "(m->omega - m->omega1) * (geq[i] - gst[i])", "(m->omega - m->omega1) * (gst[i] - geq[i])"),
     ("omega1_formula", "2.0 * Pr * omega / (2.0 - omega + Pr * omega)", "2.0 * Pr * omega / (2.0 + omega - Pr * omega)"),
     ("operator_drops_power", "r.c[k - 1] += T * (double)k * A->c[k];", "r.c[k - 1] += T * A->c[k];"),
-    ("temperature_kinetic_term", "m->T = (E - 0.5 * u2) / Cv;", "m->T = (E - u2) / Cv;"),
+    ("temperature_kinetic_term", "m->T = orc_temperature(cv, E - 0.5 * u2);", "m->T = orc_temperature(cv, E - u2);"),
     ("stream_wrong_direction", "long sh[3] = {-c[0], -c[1], -c[2]};", "long sh[3] = {c[0], c[1], c[2]};"),
     ("clamp_off_by_one", "if (r > n - 1) r = n - 1;", "if (r > n - 1) r = n - 2;"),
     ("power_law_inverted", "pow(T / p->T_ref, p->visc_exp)", "pow(p->T_ref / T, p->visc_exp)"),
     ("central_half_dropped", "out[n] = 0.5 * (Qt[np] - Qt[nm]);", "out[n] = (Qt[np] - Qt[nm]);"),
     ("viscosity_uses_pressure_wrong", "return 1.0 / (mu / (rho * T) + 0.5);", "return 1.0 / (mu / rho + 0.5);"),
+    ("internal_energy_half_dropped", "cv[1] * T * T / 2.0", "cv[1] * T * T"),
+    ("newton_step_sign", "    T -= dT;", "    T += dT;"),
+    ("geq_ignores_caloric_law", "double s = U;", "double s = 2.5 * T;"),
+    ("sound_speed_gamma_inverted", "gam = (cvT + 1.0) / cvT;", "gam = cvT / (cvT + 1.0);"),
 ]
 
 
