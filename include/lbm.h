@@ -78,6 +78,10 @@ typedef struct {
   int deriv_scheme;     /* LBM_DERIV_UPWIND (default) or LBM_DERIV_CENTRAL */
   int tile[3];          /* launch shape of the step kernel: x width, y width (D3Q27), march chunk; 0 = default */
   double u_ref[3];      /* reference velocity of FP32 deviations (|u_ref_a| < 1); default 0 */
+  double cv_poly[3];    /* caloric law (Sec. II.A, Eq. (6)): C_v(T) = cv_poly[0] + cv_poly[1] T + cv_poly[2] T^2,
+                           U(T) = its integral from 0, T recovered from U by Newton's method; needs
+                           cv_poly[0] > 0 and cv_poly[1], cv_poly[2] >= 0.  All zero (default): the
+                           constant C_v = 1/(gamma - 1), and gamma is used for nothing else */
 } lbm_options;
 
 /* Fills *opt with the defaults above. */

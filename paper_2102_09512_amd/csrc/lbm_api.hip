@@ -80,8 +80,12 @@ void fill_step_params(const lbm::Ctx* c, const lbm::Tile& t, lbm::StepParams& p)
   p.chunks = (nm + p.chunk_len - 1) / p.chunk_len;
   p.nblocks = p.tiles_x * p.tiles_y * p.chunks;
   p.deriv = c->opt.deriv_scheme;
-  p.Cv = 1.0 / (c->gamma - 1.0);
-  p.inv_Cv = c->gamma - 1.0;
+  const double* cvp = c->opt.cv_poly;
+  p.caloric = (cvp[0] != 0.0 || cvp[1] != 0.0 || cvp[2] != 0.0) ? 1 : 0;
+  p.Cv = p.caloric ? cvp[0] : 1.0 / (c->gamma - 1.0);
+  p.inv_Cv = p.caloric ? 1.0 / cvp[0] : c->gamma - 1.0;
+  p.cv1 = p.caloric ? cvp[1] : 0.0;
+  p.cv2 = p.caloric ? cvp[2] : 0.0;
   p.Pr = c->Pr;
   p.gamma = c->gamma;
   p.mu0 = c->mu;
@@ -95,6 +99,8 @@ void fill_step_params(const lbm::Ctx* c, const lbm::Tile& t, lbm::StepParams& p)
     // its exact FP64 inverse.
     p.Cv = (double)(float)p.Cv;
     p.inv_Cv = 1.0 / p.Cv;
+    p.cv1 = (double)(float)p.cv1;
+    p.cv2 = (double)(float)p.cv2;
     p.rho0 = (double)(float)c->opt.rho_ref;
     p.T0 = (double)(float)c->opt.T_ref;
     double u2 = 0.0;
@@ -117,9 +123,10 @@ void fill_step_params(const lbm::Ctx* c, const lbm::Tile& t, lbm::StepParams& p)
       p.b0[a][1] = 0.5 * u0 * u0 - B2;
       p.b0[a][2] = 0.5 * (B1 + B2);
     }
-    p.rhoE0 = p.rho0 * (p.Cv * p.T0 + 0.5 * u2);  // sum_i g_i of the reference
+    p.U0 = p.caloric ? lbm::caloric_u(p.Cv, p.cv1, p.cv2, p.T0) : p.Cv * p.T0;
+    p.rhoE0 = p.rho0 * (p.U0 + 0.5 * u2);  // sum_i g_i of the reference
   } else {
-    p.rho0 = p.T0 = p.rhoE0 = 0.0;
+    p.rho0 = p.T0 = p.rhoE0 = p.U0 = 0.0;
     for (int a = 0; a < 3; ++a) {
       p.u0[a] = p.j0[a] = p.P0[a] = 0.0;
       for (int c = 0; c < 3; ++c) p.psi0[a][c] = p.b0[a][c] = 0.0;
@@ -191,6 +198,10 @@ int lbm_create(lbm_handle* out, int lattice, const int64_t dims[3], double gamma
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(opt.u_ref[a]) || std::fabs(opt.u_ref[a]) >= 1.0)
       return fail(LBM_EINVAL, "lbm_create: u_ref components must be finite and |u_ref| < 1");
+  if (opt.cv_poly[0] != 0.0 || opt.cv_poly[1] != 0.0 || opt.cv_poly[2] != 0.0)
+    if (!(opt.cv_poly[0] > 0.0 && opt.cv_poly[1] >= 0.0 && opt.cv_poly[2] >= 0.0) ||
+        !std::isfinite(opt.cv_poly[0] + opt.cv_poly[1] + opt.cv_poly[2]))
+      return fail(LBM_EINVAL, "lbm_create: cv_poly needs cv_poly[0] > 0 and cv_poly[1], cv_poly[2] >= 0 (finite)");
   const int64_t N = dims[0] * dims[1] * dims[2];
   if (N > ((int64_t)1 << 31) - 1024) return fail(LBM_EINVAL, "lbm_create: more than 2^31 nodes");
 

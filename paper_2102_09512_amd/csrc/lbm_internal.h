@@ -24,16 +24,27 @@ struct StepParams {
   int nblocks;
   int deriv;            // LBM_DERIV_*
   // Reference state (rho0, u0, T0) of the FP32 deviation storage; all zero
-  // for FP64 storage.  rhoE0 = rho0 (Cv T0 + |u0|^2/2) and j0 = rho0 u0 are
+  // for FP64 storage.  rhoE0 = rho0 (U(T0) + |u0|^2/2) and j0 = rho0 u0 are
   // the reference's energy and momentum; P0, psi0, b0 the per-axis factors
   // of its product-form populations (see NodeConsts).
   double rho0, T0, rhoE0;
   double u0[3], j0[3], P0[3], psi0[3][3], b0[3][3];
   float u0f[3], P0f[3], psi0f[3][3], b0f[3][3];
+  // Caloric law: C_v(T) = Cv + cv1 T + cv2 T^2 when caloric != 0, else the
+  // constant Cv; U0 = U(T0).
   double Cv, inv_Cv, Pr;
+  double cv1, cv2, U0;
+  int caloric;
   double mu0, visc_exp, inv_Tref;
   double gamma;
 };
+
+// Caloric law (Eq. (6)): C_v(T) = c0 + c1 T + c2 T^2 and U(T) its integral
+// from 0.
+__host__ __device__ inline double caloric_cv(double c0, double c1, double c2, double T) { return c0 + T * (c1 + T * c2); }
+__host__ __device__ inline double caloric_u(double c0, double c1, double c2, double T) {
+  return T * (c0 + T * (0.5 * c1 + T * (c2 / 3.0)));
+}
 
 // Launch shape of the step kernel (compile-time instantiations).
 struct Tile {

@@ -85,6 +85,10 @@ __device__ inline NodeConsts node_consts(const StepParams& p) {
   k.T0 = p.T0;
   k.inv_Cv = p.inv_Cv;
   k.Cv = p.Cv;
+  k.cv1 = p.cv1;
+  k.cv2 = p.cv2;
+  k.U0 = p.U0;
+  k.caloric = p.caloric;
   k.Pr = p.Pr;
   k.mu0 = p.mu0;
   k.visc_exp = p.visc_exp;
@@ -524,7 +528,8 @@ __global__ void __launch_bounds__(256) fields_kernel(const S* __restrict__ pops,
   const double rho = p.rho0 + s0;
   const double ux = (p.j0[0] + jx) / rho, uy = (p.j0[1] + jy) / rho, uz = (D == 3) ? (p.j0[2] + jz) / rho : 0.0;
   const double rhoE = p.rhoE0 + se;
-  const double T = (rhoE / rho - 0.5 * (ux * ux + uy * uy + uz * uz)) * p.inv_Cv;
+  const double e = rhoE / rho - 0.5 * (ux * ux + uy * uy + uz * uz);  // U(T)
+  const double T = p.caloric ? p.T0 + caloric_step(p.Cv, p.cv1, p.cv2, p.T0, e - p.U0) : e * p.inv_Cv;
   fields[n] = rho;
   fields[N + n] = ux;
   fields[2 * N + n] = uy;
@@ -606,7 +611,12 @@ __global__ void __launch_bounds__(256) diag_kernel(const double* __restrict__ F,
     acc[5] += 0.5 * rho * uu;
     acc[6] += div * div;
     acc[7] += uu;
-    acc[8] += sqrt(p.gamma * T);
+    double gam = p.gamma;  // C_p / C_v at T (Mayer: C_p = C_v + 1)
+    if (p.caloric) {
+      const double cvT = caloric_cv(p.Cv, p.cv1, p.cv2, T);
+      gam = (cvT + 1.0) / cvT;
+    }
+    acc[8] += sqrt(gam * T);
     acc[9] += rho * rho;
     acc[10] += vort2;
     acc[11] += mu * vort2;
@@ -844,10 +854,12 @@ __global__ void __launch_bounds__(256) fields_plus_kernel(const double* __restri
   newf[4 * N + n] = k * oldf[4 * N + n] + dT[n];
 }
 
-// coarse node: means of rho, rho u and rho E over its factor^D fine nodes
+// coarse node: means of rho, rho u and rho E over its factor^D fine nodes;
+// T from U(T) = E - |u|^2 / 2 with the caloric law of p
 __global__ void __launch_bounds__(256) filter_kernel(const double* __restrict__ fields, long long N, int nx, int ny,
-                                                     int nz, int f, int fz, int D, double Cv, double* __restrict__ rho,
-                                                     double* __restrict__ u, double* __restrict__ T) {
+                                                     int nz, int f, int fz, int D, const StepParams p,
+                                                     double* __restrict__ rho, double* __restrict__ u,
+                                                     double* __restrict__ T) {
   const int cx = nx / f, cy = ny / f, cz = nz / fz;
   const long long Nc = (long long)cx * cy * cz;
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -872,7 +884,8 @@ __global__ void __launch_bounds__(256) filter_kernel(const double* __restrict__ 
   }
   const double cnt = (double)f * f * fz;
   rho[c] = sr / cnt;
-  T[c] = (se * inv - 0.5 * u2) / Cv;
+  const double e = se * inv - 0.5 * u2;
+  T[c] = p.caloric ? caloric_step(p.Cv, p.cv1, p.cv2, 0.0, e) : e / p.Cv;
 }
 
 hipError_t launch_fields_add(const Ctx& c, void* pops, const double* oldf, const double* newf) {
@@ -908,7 +921,7 @@ hipError_t launch_filter(const Ctx& c, const double* fields, int factor, double*
   const int fz = c.lattice == 3 ? factor : 1;
   const long long Nc = (c.n[0] / factor) * (c.n[1] / factor) * (c.n[2] / fz);
   hipLaunchKernelGGL(filter_kernel, dim3((unsigned)((Nc + 255) / 256)), dim3(256), 0, c.stream, fields, c.N,
-                     (int)c.n[0], (int)c.n[1], (int)c.n[2], factor, fz, c.lattice, c.sp.Cv, rho, u, T);
+                     (int)c.n[0], (int)c.n[1], (int)c.n[2], factor, fz, c.lattice, c.sp, rho, u, T);
   return hipGetLastError();
 }
 

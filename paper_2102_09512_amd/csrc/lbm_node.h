@@ -62,6 +62,8 @@ struct NodeMoments {
 struct NodeConsts {
   double rho0, T0;
   double inv_Cv, Cv, Pr;
+  double cv1, cv2, U0;  // caloric law (see caloric_*)
+  int caloric;
   double mu0, visc_exp, inv_Tref;
   double u0[3], P0[3], psi0[3][3], b0[3][3];
   float u0f[3], P0f[3], psi0f[3][3], b0f[3][3];
@@ -78,6 +80,26 @@ template <typename R>
 __device__ inline R ref_psi0(const NodeConsts& k, int a, int c) { return ref(R(k.psi0[a][c]), k.psi0f[a][c]); }
 template <typename R>
 __device__ inline R ref_b0(const NodeConsts& k, int a, int c) { return ref(R(k.b0[a][c]), k.b0f[a][c]); }
+
+// Caloric law (Eq. (6)), with caloric_cv and caloric_u: U(T0 + dT) - U(T0)
+// is formed from dT directly, so a small step loses nothing to cancellation.
+template <typename R>
+__device__ inline R caloric_du(R c0, R c1, R c2, R T0, R dT) {
+  return dT * (c0 + c1 * (T0 + (R)0.5 * dT) + c2 * (T0 * T0 + T0 * dT + dT * dT * (R)(1.0 / 3.0)));
+}
+// dT with U(T0 + dT) - U(T0) = dU: Newton's method from the step of the
+// constant C_v(T0), until the correction is below 1e-15 of T (U is increasing
+// and convex for c0 > 0, c1, c2 >= 0, so the iterates converge monotonically
+// after the first step); at most 40 steps.
+__device__ inline double caloric_step(double c0, double c1, double c2, double T0, double dU) {
+  double dT = dU / caloric_cv(c0, c1, c2, T0);
+  for (int it = 0; it < 40; ++it) {
+    const double h = (caloric_du<double>(c0, c1, c2, T0, dT) - dU) / caloric_cv(c0, c1, c2, T0 + dT);
+    dT -= h;
+    if (fabs(h) <= 1e-15 * fabs(T0 + dT)) break;
+  }
+  return dT;
+}
 
 // Reciprocal: the hardware approximation (about 1 ulp) in FP32, IEEE
 // division in FP64.
@@ -116,9 +138,10 @@ __device__ inline void nonequilibrium_pressure(NodeMoments<R>& m, const R* p, co
 
 // u, u - u0 and T - T0 from the sums of the stored values (s0 = sum f,
 // j = sum c f, se = sum g), all in deviation form: u - u0 = (j - drho u0) / rho
-// and rho Cv (T - T0) = se - (1/2) sum_a [rho0 du_a (u_a + u0_a) + drho u_a^2]
-// - drho Cv T0, which follow from rho u = rho0 u0 + j and
-// rho E = rho0 (Cv T0 + |u0|^2 / 2) + se.
+// and rho (U(T) - U(T0)) = se - (1/2) sum_a [rho0 du_a (u_a + u0_a) + drho u_a^2]
+// - drho U(T0), which follow from rho u = rho0 u0 + j and
+// rho E = rho0 (U(T0) + |u0|^2 / 2) + se; then T - T0 = that / C_v for a
+// constant C_v, or by caloric_step for a general law.
 // The sums and this recovery are done in FP64 for every storage precision.
 template <int D, typename R>
 __device__ inline void velocity_temperature(NodeMoments<R>& m, double s0, const double* j, double se,
@@ -138,7 +161,8 @@ __device__ inline void velocity_temperature(NodeMoments<R>& m, double s0, const 
       m.du[a] = m.u[a] = (R)0;
     }
   }
-  const double dT = (se - 0.5 * ke - s0 * (k.Cv * k.T0)) * irho * k.inv_Cv;
+  const double dU = (se - 0.5 * ke - s0 * k.U0) * irho;  // U(T) - U(T0)
+  const double dT = k.caloric ? caloric_step(k.Cv, k.cv1, k.cv2, k.T0, dU) : dU * k.inv_Cv;
   m.drho = (R)s0;
   m.rho = (R)rho;
   m.irho = (R)irho;
@@ -413,9 +437,15 @@ struct EqBuilder {
       F[a] = axis_f<R, DEV>(m.u[a], m.du[a], dP, ref_P0<R>(k, a));
       G[a] = axis_g<R, DEV>(m.u[a], m.du[a], u0, m.T, m.dT, T0);
     }
-    eps = (R)k.Cv * m.T;
-    deps = (R)k.Cv * m.dT;
-    eps0 = (R)k.Cv * T0;
+    if (k.caloric) {  // U(T) = U(T0) + (U(T) - U(T0))
+      deps = caloric_du<R>((R)k.Cv, (R)k.cv1, (R)k.cv2, T0, m.dT);
+      eps0 = (R)k.U0;
+      eps = eps0 + deps;
+    } else {
+      eps = (R)k.Cv * m.T;
+      deps = (R)k.Cv * m.dT;
+      eps0 = (R)k.Cv * T0;
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       hx[c] = m.drho * F[0].psi[c] + (DEV ? rho0 * F[0].dpsi[c] : (R)0);

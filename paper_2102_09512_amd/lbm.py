@@ -41,7 +41,7 @@ class lbm_options(C.Structure):
     _fields_ = [
         ("precision", C.c_int), ("bc", C.c_int * 3), ("visc_exponent", C.c_double),
         ("T_ref", C.c_double), ("rho_ref", C.c_double), ("deriv_scheme", C.c_int),
-        ("tile", C.c_int * 3), ("u_ref", C.c_double * 3),
+        ("tile", C.c_int * 3), ("u_ref", C.c_double * 3), ("cv_poly", C.c_double * 3),
     ]
 
 
@@ -169,7 +169,8 @@ def lbm_default_options() -> lbm_options:
 
 
 def lbm_create(lattice, dims, gamma, Pr, mu, options: lbm_options | None = None, *, precision=None, bc=None,
-               visc_exponent=None, T_ref=None, rho_ref=None, deriv_scheme=None, tile=None, u_ref=None) -> int:
+               visc_exponent=None, T_ref=None, rho_ref=None, deriv_scheme=None, tile=None, u_ref=None,
+               cv_poly=None) -> int:
     o = options if options is not None else lbm_default_options()
     if precision is not None:
         o.precision = precision
@@ -190,6 +191,9 @@ def lbm_create(lattice, dims, gamma, Pr, mu, options: lbm_options | None = None,
     if u_ref is not None:
         for a in range(len(u_ref)):
             o.u_ref[a] = float(u_ref[a])
+    if cv_poly is not None:
+        for k in range(3):
+            o.cv_poly[k] = float(cv_poly[k])
     d = (C.c_int64 * 3)(*[int(v) for v in (list(dims) + [1] * (3 - len(dims)))])
     h = C.c_void_p()
     _check(_L.lbm_create(C.byref(h), int(lattice), d, float(gamma), float(Pr), float(mu), C.byref(o)))

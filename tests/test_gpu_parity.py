@@ -26,13 +26,14 @@ def rel(a, b):
 
 
 def run_gpu(D, dims, fields, steps, mu, Pr=0.71, gamma=1.4, fp32=False, bc=(0, 0, 0), visc_exp=0.0, T_ref=0.15,
-            deriv=0, device_io=True, tile=None, want_state=True, want_diag=False, u_ref=None):
+            deriv=0, device_io=True, tile=None, want_state=True, want_diag=False, u_ref=None, cv=None):
     lbm = _lbm()
     print(f"[gpu case] D={D} dims={dims} steps={steps} fp32={fp32} bc={bc} deriv={deriv} tile={tile} "
           f"io={'device' if device_io else 'host'}", flush=True)
     rho, u, T = fields
     h = lbm.lbm_create(D, dims, gamma, Pr, mu, precision=lbm.LBM_FP32_DEV if fp32 else lbm.LBM_FP64, bc=bc,
-                       visc_exponent=visc_exp, T_ref=T_ref, rho_ref=1.0, deriv_scheme=deriv, tile=tile, u_ref=u_ref)
+                       visc_exponent=visc_exp, T_ref=T_ref, rho_ref=1.0, deriv_scheme=deriv, tile=tile, u_ref=u_ref,
+                       cv_poly=cv)
     try:
         lbm.lbm_set_stream(h, torch.cuda.current_stream())
         if device_io:
@@ -59,8 +60,9 @@ def run_gpu(D, dims, fields, steps, mu, Pr=0.71, gamma=1.4, fp32=False, bc=(0, 0
     return out, state, diag
 
 
-def run_oracle(D, dims, fields, steps, mu, Pr=0.71, gamma=1.4, bc=(0, 0, 0), visc_exp=0.0, T_ref=0.15, deriv=0):
-    s = oracle.Sim(D, dims, gamma=gamma, Pr=Pr, mu=mu, visc_exp=visc_exp, T_ref=T_ref, bc=bc, deriv=deriv)
+def run_oracle(D, dims, fields, steps, mu, Pr=0.71, gamma=1.4, bc=(0, 0, 0), visc_exp=0.0, T_ref=0.15, deriv=0,
+               cv=None):
+    s = oracle.Sim(D, dims, gamma=gamma, Pr=Pr, mu=mu, visc_exp=visc_exp, T_ref=T_ref, bc=bc, deriv=deriv, cv=cv)
     s.init(*fields)
     s.step(steps)
     return s
@@ -459,3 +461,66 @@ def test_fp32_d2q9_tiles(tile):
     out, _, _ = run_gpu(2, (300, 70), (rho, u, T), 80, fp32=True, want_state=False, tile=tile, u_ref=ur, **kw)
     s = run_oracle(2, (300, 70), (rho, u, T), 80, **kw)
     check_fp32_with_floor(2, (300, 70), (rho, u, T), 80, out, s, u_ref=ur, **kw)
+
+
+# ---- general caloric law (Sec. II.A, Eq. (6)) --------------------------------
+
+CV_LAW = (1.5, 5.0, 20.0)  # C_v(T) = 1.5 + 5 T + 20 T^2
+
+
+@pytest.mark.parametrize("D,dims", [(2, (40, 33)), (3, (21, 18, 13))])
+def test_fp64_general_caloric_law_100_steps(D, dims):
+    """U(T) in g^eq and Newton's temperature recovery: FP64 within 1e-12 of
+    the oracle after 100 steps, on fields with strong temperature contrast,
+    with the power-law viscosity."""
+    f = I.smooth_random(D, dims, seed=21, u_amp=0.12, T_amp=0.06)
+    kw = dict(mu=0.02, Pr=0.7, visc_exp=0.76, T_ref=0.15, cv=CV_LAW)
+    out, state, diag = run_gpu(D, dims, f, 100, want_diag=True, **kw)
+    s = run_oracle(D, dims, f, 100, **kw)
+    check_fields(out, s, 1e-12)
+    check_pops(state, s, 1e-12)
+    ref = s.diagnostics()
+    assert diag["cs_sum"] == pytest.approx(ref["cs"], rel=1e-12)
+    assert diag["energy"] == pytest.approx(ref["energy"], rel=1e-12)
+
+
+def test_fp32_general_caloric_law_turbulence():
+    """FP32 deviation storage with the general law: fields within 1e-5 of the
+    FP64 oracle after 100 steps (or twice the case's FP32 conditioning floor)."""
+    D, dims = 3, (24, 24, 24)
+    f = I.turbulence(3, 24, seed=5, Ma_t=0.3)
+    kw = dict(mu=0.02, Pr=0.7, visc_exp=0.76, T_ref=0.15, cv=CV_LAW)
+    out, _, _ = run_gpu(D, dims, f, 100, fp32=True, want_state=False, **kw)
+    s = run_oracle(D, dims, f, 100, **kw)
+    check_fp32_with_floor(D, dims, f, 100, out, s, **kw)
+
+
+def test_filter_with_general_caloric_law():
+    """The box filter recovers T from the filtered energy with the same law."""
+    lbm = _lbm()
+    dims = (16, 12, 8)
+    rho, u, T = I.smooth_random(3, dims, seed=22, u_amp=0.1, T_amp=0.05)
+    h = lbm.lbm_create(3, dims, 1.4, 0.7, 0.02, cv_poly=CV_LAW)
+    try:
+        lbm.lbm_init_fields(h, rho, u, T)
+        lbm.lbm_step(h, 3)
+        mom = [np.zeros(a.shape) for a in (rho, u, T)]
+        lbm.lbm_moments(h, *mom)
+        cs = (2, 3, 4)
+        out = (np.zeros(cs), np.zeros((3,) + cs), np.zeros(cs))
+        lbm.lbm_filter_moments(h, 4, *out)
+    finally:
+        lbm.lbm_destroy(h)
+    r, m, TT = mom
+    U = lambda t: CV_LAW[0] * t + CV_LAW[1] * t ** 2 / 2 + CV_LAW[2] * t ** 3 / 3
+    E = U(TT) + 0.5 * (m ** 2).sum(0)
+
+    def blocks(a):
+        return a.reshape(2, 4, 3, 4, 4, 4).mean(axis=(1, 3, 5))
+
+    rc = blocks(r)
+    uc = np.stack([blocks(r * m[a]) / rc for a in range(3)])
+    e = blocks(r * E) / rc - 0.5 * (uc ** 2).sum(0)
+    assert np.abs(out[0] - rc).max() <= 1e-14
+    assert np.abs(out[1] - uc).max() <= 1e-14
+    assert np.abs(U(out[2]) - e).max() <= 1e-14 * np.abs(e).max()
