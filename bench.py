@@ -19,6 +19,20 @@ per step (a batch), the launch shape chosen by the library's autotuner and
 the steps replayed from a captured HIP graph.  value = aggregate MLUPS over
 all boxes.
 
+--workload learned64: the learned coarse-grid corrector.  Fine D3Q27 runs at
+256^3 (32 training seeds, Ma_t uniform in [0.3, 0.6]) box-filtered to 64^3
+give teacher-forced training pairs; a 4-layer 3x3x3 convolutional network (32
+channels, bf16 matrix cores, FP32 accumulation) is trained on the GPU for
+--steps epochs; on 4 held-out seeds the corrected 64^3 run, the plain 64^3
+run and plain runs on finer grids are judged by the kinetic-energy spectrum
+error against the filtered 256^3 run (RMS of log E over shells 1..32).
+value = the corrected run's error; the plain run given the same wall time is
+reported beside it.
+
+--workload nnforward64: the corrector network's forward pass alone at 64^3
+(He-normal weights, normalised random input), --steps timed passes: the
+bf16 matrix-core roofline of the convolution kernels, for profiling.
+
 One timed step = one lbm_step (one launch of the fused kernel) over the whole
 box; the diagnostics reduction runs every --diag-every steps inside the timed
 region.  Prints one JSON line (metric MLUPS) with the roofline of the step
@@ -194,12 +208,171 @@ def run_ensemble(args, torch, lbm, dev):
     return out
 
 
+def run_learned(args, torch, lbm, dev):
+    """The learned workload (see the module docstring)."""
+    import numpy as np
+
+    from paper_2102_09512_amd import corrector as Cr
+
+    w = Cr.Workload()
+    tr = Cr.training_seeds(args.train_seeds)
+    ev = Cr.evaluation_seeds(args.eval_seeds)
+    t0 = time.perf_counter()
+    pairs = Cr.generate_pairs(w, *tr, log=_log)
+    t_data = time.perf_counter() - t0
+    res = Cr.train(w, pairs, epochs=args.steps, lr=args.lr, batch=4, log=_log)
+    del pairs
+    vp = Cr.generate_pairs(w, *ev, log=_log)
+    hv = vp.cpu().numpy().astype(np.float64)
+    out_std = res.scaling[2]
+    zero_loss = float(np.mean(((hv[:, 0] - hv[:, 1]) / out_std[None, :, None]) ** 2))
+    val_loss = Cr.validation_loss(res.net, vp)
+    _log(f"[bench] validation loss {val_loss:.4f} (no correction {zero_loss:.4f})")
+    # forward pass of the network at 64^3: bf16 matrix-core roofline
+    nc = w.n_coarse
+    V = nc ** 3
+    stream = torch.cuda.current_stream(dev)
+    lbm.lbm_nn_set_stream(res.net, stream)
+    x = vp[0, 0].contiguous()
+    y = torch.empty((5, V), dtype=torch.float32, device=dev)
+    for _ in range(3):
+        lbm.lbm_nn_forward(res.net, x, y)
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        lbm.lbm_nn_forward(res.net, x, y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fwd_s = e0.elapsed_time(e1) / 1e3 / reps
+    ch = w.channels
+    flops = sum(2 * 27 * ch[l] * ch[l + 1] for l in range(len(ch) - 1)) * V
+    tflops = flops / fwd_s / 1e12
+    lbm.lbm_nn_set_stream(res.net, None)
+    del vp, x, y
+    rows = Cr.evaluate(w, res.net, *ev, log=_log)
+    summ = Cr.summarize(rows)
+    lbm.lbm_nn_destroy(res.net)
+    out = {
+        "metric": "kinetic-energy spectrum error at equal wall time, learned vs plain (D3Q27 64^3)",
+        "value": round(summ["learned"], 5),
+        "unit": "RMS of log(E/E_ref) over shells 1-32",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 0,
+        "ms_per_step": round(res.seconds / max(args.steps, 1) * 1e3, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 populations, bf16 network (fp32 accumulation)",
+        "data": "synthetic (seeded, no dataset); reference = the method's own 256^3 runs, box-filtered",
+        "config": {"workload": "learned corrector: D3Q27 decaying turbulence 64^3 FP32 + 4-layer 3x3x3 conv "
+                               "(32 ch), trained on 256^3 runs box-filtered 4^3 -> 64^3",
+                   "training_seeds": len(tr[0]), "evaluation_seeds": ev[0], "Ma_t_eval": ev[1],
+                   "correction_every_coarse_steps": w.every, "coarse_steps": w.coarse_steps,
+                   "fine_steps": w.coarse_steps * w.factor, "epochs": args.steps, "parallelism": "single GPU"},
+        "plain_coarse_error": round(summ["plain_coarse"], 5),
+        "plain_equal_time_error": round(summ["plain_equal_time"], 5),
+        "equal_time_grids": summ["equal_time_grids"],
+        "wins_equal_time": f"{summ['wins_equal_time']}/{summ['seeds']}",
+        "per_seed": [{"seed": r["seed"], "Ma_t": round(r["Ma_t"], 4),
+                      "learned": [round(r["learned"]["error"], 5), round(1e3 * r["learned"]["seconds"], 2)],
+                      "plain": [[p["n"], round(p["error"], 5), round(1e3 * p["seconds"], 2)] for p in r["plain"]]}
+                     for r in rows],
+        "training": {"pairs": len(tr[0]) * w.windows, "data_seconds": round(t_data, 1),
+                     "train_seconds": round(res.seconds, 1), "loss_first_epoch": round(res.history[0], 5),
+                     "loss_last_epoch": round(res.history[-1], 5), "validation_loss": round(val_loss, 5),
+                     "no_correction_loss": round(zero_loss, 5)},
+        "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(tflops / 2500.0, 5), "traffic": None,
+                     "kernel": "network forward at 64^3 (4 conv launches + input packing)",
+                     "avg_forward_ms": round(fwd_s * 1e3, 4), "algorithmic_flops_per_forward": flops},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_forward_baseline(w)
+    return out
+
+
+def run_nnforward(args, torch, lbm, dev):
+    """Forward passes of the corrector network at 64^3 (see the module docstring)."""
+    import numpy as np
+
+    from paper_2102_09512_amd import corrector as Cr
+
+    w = Cr.Workload()
+    nc = w.n_coarse
+    V = nc ** 3
+    net = lbm.lbm_nn_create(list(w.channels), (nc, nc, nc))
+    try:
+        lbm.lbm_nn_set_params(net, Cr.initial_params(w.channels, seed=0, last_gain=1.0))
+        lbm.lbm_nn_set_scaling(net, np.zeros(5), np.ones(5))
+        stream = torch.cuda.current_stream(dev)
+        lbm.lbm_nn_set_stream(net, stream)
+        g = torch.Generator(device="cpu").manual_seed(0)
+        x = torch.randn((5, V), generator=g, dtype=torch.float32).to(dev)
+        y = torch.empty((5, V), dtype=torch.float32, device=dev)
+        for _ in range(max(args.warmup, 1)):
+            lbm.lbm_nn_forward(net, x, y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            lbm.lbm_nn_forward(net, x, y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        fwd_s = e0.elapsed_time(e1) / 1e3 / args.steps
+    finally:
+        lbm.lbm_nn_destroy(net)
+    ch = w.channels
+    flops = sum(2 * 27 * ch[l] * ch[l + 1] for l in range(len(ch) - 1)) * V
+    tflops = flops / fwd_s / 1e12
+    out = {
+        "metric": "TFLOP/s (corrector network forward, 4 bf16 3x3x3 conv layers at 64^3)",
+        "value": round(tflops, 2), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16 (fp32 accumulation)", "data": "synthetic (seeded)",
+        "config": {"workload": "corrector network forward 64^3, channels 5-32-32-32-5", "nodes": V,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(tflops / 2500.0, 5), "traffic": None,
+                     "kernel": "network forward (4 conv launches + input packing)",
+                     "avg_forward_ms": round(fwd_s * 1e3, 4), "algorithmic_flops_per_forward": flops},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_forward_baseline(w)
+    return out
+
+
+def cpu_forward_baseline(w):
+    """The oracle's FP64 network forward on a 32^3 sample, scaled to forward
+    passes of the 64^3 grid per second."""
+    import numpy as np
+
+    from oracle import convnet as N
+
+    r = np.random.default_rng(0)
+    p = r.normal(0.0, 0.1, N.param_count(list(w.channels)))
+    x = r.normal(size=(w.channels[0], 32, 32, 32))
+    t0 = time.perf_counter()
+    N.forward(p, list(w.channels), x)
+    dt = time.perf_counter() - t0
+    per64 = dt * (w.n_coarse / 32) ** 3
+    return {"value": round(1.0 / per64, 4), "unit": "forward passes per second at 64^3", "cores": 1,
+            "kind": "oracle", "sample": f"one forward at 32^3 ({dt:.1f} s), scaled by the node count"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["turbulence3d", "shockvortex2d", "ensemble2d"], default="turbulence3d")
+    ap.add_argument("--workload", choices=["turbulence3d", "shockvortex2d", "ensemble2d", "learned64", "nnforward64"],
+                    default="turbulence3d")
+    ap.add_argument("--train-seeds", type=int, default=32, help="learned64: training seeds")
+    ap.add_argument("--eval-seeds", type=int, default=4, help="learned64: held-out seeds")
+    ap.add_argument("--lr", type=float, default=1e-3, help="learned64: Adam learning rate")
     ap.add_argument("--graph-steps", type=int, default=50, help="ensemble2d: steps per captured HIP graph")
     ap.add_argument("--n", type=int, default=0, help="box edge (default 256 for turbulence3d, 1024 for shockvortex2d)")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
@@ -225,6 +398,12 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "ensemble2d":
         print(json.dumps(run_ensemble(args, torch, lbm, dev)), flush=True)
+        return
+    if args.workload == "learned64":
+        print(json.dumps(run_learned(args, torch, lbm, dev)), flush=True)
+        return
+    if args.workload == "nnforward64":
+        print(json.dumps(run_nnforward(args, torch, lbm, dev)), flush=True)
         return
     n = args.n or (256 if args.workload == "turbulence3d" else 1024)
     _log(f"[bench] generating the {args.workload} input, n = {n}")

@@ -146,9 +146,10 @@ def test_adam_step_matches_reference():
 
 def test_training_reduces_the_loss():
     """A target that is a fixed smooth function of the input: the network
-    learns it (the loss falls tenfold in 150 Adam steps on one sample set)."""
+    learns it (the loss falls tenfold in 150 Adam steps on one sample set; the
+    FP64 reference network trained the same way falls from 6.5e-3 to 1.5e-4)."""
     lbm = _lbm()
-    shape = (4, 8, 32)
+    shape = (8, 8, 32)
     xs, ts = [], []
     for s in range(4):
         rho, u, T = I.smooth_random(3, shape[::-1], seed=30 + s, u_amp=0.1)
