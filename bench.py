@@ -223,9 +223,7 @@ def run_learned(args, torch, lbm, dev):
     res = Cr.train(w, pairs, epochs=args.steps, lr=args.lr, batch=4, log=_log)
     del pairs
     vp = Cr.generate_pairs(w, *ev, log=_log)
-    hv = vp.cpu().numpy().astype(np.float64)
-    out_std = res.scaling[2]
-    zero_loss = float(np.mean(((hv[:, 0] - hv[:, 1]) / out_std[None, :, None]) ** 2))
+    zero_loss = Cr.no_correction_loss(w, vp, res.scaling[2])
     val_loss = Cr.validation_loss(res.net, vp)
     _log(f"[bench] validation loss {val_loss:.4f} (no correction {zero_loss:.4f})")
     # forward pass of the network at 64^3: bf16 matrix-core roofline
@@ -234,7 +232,7 @@ def run_learned(args, torch, lbm, dev):
     stream = torch.cuda.current_stream(dev)
     lbm.lbm_nn_set_stream(res.net, stream)
     x = vp[0, 0].contiguous()
-    y = torch.empty((5, V), dtype=torch.float32, device=dev)
+    y = torch.empty((w.channels[-1], V), dtype=torch.float32, device=dev)
     for _ in range(3):
         lbm.lbm_nn_forward(res.net, x, y)
     reps = 20
@@ -267,7 +265,7 @@ def run_learned(args, torch, lbm, dev):
         "dtype": "f32 populations, bf16 network (fp32 accumulation)",
         "data": "synthetic (seeded, no dataset); reference = the method's own 256^3 runs, box-filtered",
         "config": {"workload": "learned corrector: D3Q27 decaying turbulence 64^3 FP32 + 4-layer 3x3x3 conv "
-                               "(32 ch), trained on 256^3 runs box-filtered 4^3 -> 64^3",
+                               "(32 ch; reads rho, u, T, corrects u), trained on 256^3 runs box-filtered 4^3 -> 64^3",
                    "training_seeds": len(tr[0]), "evaluation_seeds": ev[0], "Ma_t_eval": ev[1],
                    "correction_every_coarse_steps": w.every, "coarse_steps": w.coarse_steps,
                    "fine_steps": w.coarse_steps * w.factor, "epochs": args.steps, "parallelism": "single GPU"},
@@ -305,12 +303,12 @@ def run_nnforward(args, torch, lbm, dev):
     net = lbm.lbm_nn_create(list(w.channels), (nc, nc, nc))
     try:
         lbm.lbm_nn_set_params(net, Cr.initial_params(w.channels, seed=0, last_gain=1.0))
-        lbm.lbm_nn_set_scaling(net, np.zeros(5), np.ones(5))
+        lbm.lbm_nn_set_scaling(net, np.zeros(5), np.ones(5), np.ones(w.channels[-1]))
         stream = torch.cuda.current_stream(dev)
         lbm.lbm_nn_set_stream(net, stream)
         g = torch.Generator(device="cpu").manual_seed(0)
         x = torch.randn((5, V), generator=g, dtype=torch.float32).to(dev)
-        y = torch.empty((5, V), dtype=torch.float32, device=dev)
+        y = torch.empty((w.channels[-1], V), dtype=torch.float32, device=dev)
         for _ in range(max(args.warmup, 1)):
             lbm.lbm_nn_forward(net, x, y)
         torch.cuda.synchronize()
@@ -333,7 +331,7 @@ def run_nnforward(args, torch, lbm, dev):
         "value": round(tflops, 2), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(wall / args.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16 (fp32 accumulation)", "data": "synthetic (seeded)",
-        "config": {"workload": "corrector network forward 64^3, channels 5-32-32-32-5", "nodes": V,
+        "config": {"workload": "corrector network forward 64^3, channels " + "-".join(map(str, w.channels)), "nodes": V,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": round(tflops / 2500.0, 5), "traffic": None,

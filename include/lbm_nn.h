@@ -57,13 +57,17 @@ int lbm_nn_zero_grad(lbm_nn net);
    out_std[c] (host array of c[L] values, > 0) scales the output; out_std may
    be NULL, then out_std = std. */
 int lbm_nn_set_scaling(lbm_nn net, const double* mean, const double* std, const double* out_std);
+/* Output c of the network belongs to input field offset + c (loss and
+   correction); offset + c[L] <= c[0].  Default 0.  E.g. offset 1 with
+   c[L] = D: the network corrects the velocity only. */
+int lbm_nn_set_output_offset(lbm_nn net, int offset);
 /* y = network(normalised x): x is c[0] planes, y is c[L] planes (device). */
 int lbm_nn_forward(lbm_nn net, const float* x, float* y);
 /* Training loss of one sample and its gradients (accumulated):
-     L = mean over nodes and c < c[L] of (y_c + (x_c - t_c) / out_std_c)^2,
-   y = network(normalised x), t the target fields (c[L] planes, device); the
-   corrected field x_c + y_c out_std_c is compared with t_c in units of
-   out_std_c.
+     L = mean over nodes and c < c[L] of (y_c + (x_f - t_f) / out_std_c)^2,
+   f = offset + c, y = network(normalised x), t the target fields (c[0]
+   planes, device); the corrected field x_f + y_c out_std_c is compared with
+   t_f in units of out_std_c.
    *loss (host, may be NULL) receives L.  Synchronous. */
 int lbm_nn_loss_backward(lbm_nn net, const float* x, const float* target, double* loss);
 /* One Adam step on the accumulated gradients (scaled by grad_scale), step
@@ -77,7 +81,8 @@ int lbm_nn_fields_to_planes(int D, int64_t nodes, const double* rho, const doubl
                             void* hip_stream);
 /* Applies the corrector to a lattice Boltzmann handle whose dims equal the
    network's: reads rho, u, T (lbm_moments), runs the network and adds the
-   correction with lbm_fields_add.  Requires c[0] = c[L] = D + 2. */
+   correction y_c out_std_c to field offset + c (the other fields get none)
+   with lbm_fields_add.  Requires c[0] = D + 2. */
 int lbm_nn_correct(lbm_nn net, lbm_handle h);
 
 #ifdef __cplusplus

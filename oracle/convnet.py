@@ -8,7 +8,9 @@ Network: layer l maps c[l] channels to c[l+1]:
 s_t = (t%3 - 1, (t//3)%3 - 1, t//9 - 1) in (x, y, z), periodic; ReLU after
 every layer but the last.  Arrays are [channel][z][y][x].  The training loss of
 one sample is L = mean over nodes and channels of (y_c + (x_c - t_c)/s_c)^2
-with y = network((x - mean)/std) and s the output scale (s = std unless given).
+with y = network((x - mean)/std) and s the output scale (s = std unless given);
+output c may belong to field c + offset (a network that corrects some of its
+input fields).
 
 Everything is written out with numpy in FP64; the backward pass follows the
 chain rule layer by layer and is pinned by finite differences in the tests.
@@ -86,16 +88,18 @@ def forward(params, channels, xn, store=None):
     return h, inputs
 
 
-def loss_and_grad(params, channels, x, target, mean, std, store=None, out_std=None):
-    """Loss of one sample and its gradient with respect to the parameters."""
+def loss_and_grad(params, channels, x, target, mean, std, store=None, out_std=None, out_offset=0):
+    """Loss of one sample and its gradient with respect to the parameters;
+    output c is compared with field out_offset + c."""
     store = store or _same
     mean = np.asarray(mean, dtype=np.float64)[:, None, None, None]
     std = np.asarray(std, dtype=np.float64)[:, None, None, None]
     x = np.asarray(x, dtype=np.float64)
     C = channels[-1]
     y, inputs = forward(params, channels, (x - mean) / std, store)
-    s = std[:C] if out_std is None else np.asarray(out_std, dtype=np.float64)[:, None, None, None]
-    r = y + (x[:C] - np.asarray(target, dtype=np.float64)) / s
+    o = out_offset
+    s = std[o:o + C] if out_std is None else np.asarray(out_std, dtype=np.float64)[:, None, None, None]
+    r = y + (x[o:o + C] - np.asarray(target, dtype=np.float64)[o:o + C]) / s
     V = r[0].size
     loss = float((r ** 2).sum() / (C * V))
     d = store(2.0 * r / (C * V))  # dL/dy

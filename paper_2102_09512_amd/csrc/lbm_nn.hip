@@ -214,10 +214,12 @@ __global__ void __launch_bounds__(256) bgrad_kernel(const __bf16* __restrict__ d
   if (threadIdx.x == 0) grad_b[o] += red[0];
 }
 
-// r = y + (x - target) / out_std; loss partial sums of r^2; dout[v][c] = 2 r / (C V)
+// r_c = y_c + (x_f - target_f) / out_std_c with f = off + c; loss partial sums
+// of r^2; dout[v][c] = 2 r / (C V)
 __global__ void __launch_bounds__(256) loss_kernel(const float* __restrict__ y, const float* __restrict__ x,
                                                    const float* __restrict__ tgt, const float* __restrict__ inv_std,
-                                                   int C, int V, __bf16* __restrict__ dout, double* __restrict__ partial) {
+                                                   int C, int off, int V, __bf16* __restrict__ dout,
+                                                   double* __restrict__ partial) {
   __shared__ double red[256];
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   double s = 0.0;
@@ -227,7 +229,8 @@ __global__ void __launch_bounds__(256) loss_kernel(const float* __restrict__ y, 
     for (int c = 0; c < 32; ++c) {
       float g = 0.f;
       if (c < C) {
-        const float rr = y[(size_t)c * V + v] + (x[(size_t)c * V + v] - tgt[(size_t)c * V + v]) * inv_std[c];
+        const size_t f = (size_t)(off + c) * V + v;
+        const float rr = y[(size_t)c * V + v] + (x[f] - tgt[f]) * inv_std[c];
         s += (double)rr * rr;
         g = scale * rr;
       }
@@ -285,16 +288,22 @@ __global__ void __launch_bounds__(256) fields_to_input_kernel(const double* __re
   x[(size_t)(1 + D) * V + v] = (float)T[v];
 }
 
-// normalised correction planes -> FP64 increments drho[V], du[D V], dT[V]
+// normalised correction planes -> FP64 increments drho[V], du[D V], dT[V]:
+// output c corrects field off + c (0 rho, 1..D u, D + 1 T); fields without an
+// output get a zero increment
 __global__ void __launch_bounds__(256) output_to_increments_kernel(const float* __restrict__ y,
-                                                                   const float* __restrict__ sd, int D, int V,
-                                                                   double* __restrict__ drho, double* __restrict__ du,
-                                                                   double* __restrict__ dT) {
+                                                                   const float* __restrict__ sd, int C, int off, int D,
+                                                                   int V, double* __restrict__ drho,
+                                                                   double* __restrict__ du, double* __restrict__ dT) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
-  drho[v] = (double)y[v] * sd[0];
-  for (int a = 0; a < D; ++a) du[(size_t)a * V + v] = (double)y[(size_t)(1 + a) * V + v] * sd[1 + a];
-  dT[v] = (double)y[(size_t)(1 + D) * V + v] * sd[1 + D];
+  for (int fld = 0; fld < D + 2; ++fld) {
+    const int c = fld - off;
+    const double inc = (c >= 0 && c < C) ? (double)y[(size_t)c * V + v] * sd[c] : 0.0;
+    if (fld == 0) drho[v] = inc;
+    else if (fld <= D) du[(size_t)(fld - 1) * V + v] = inc;
+    else dT[v] = inc;
+  }
 }
 
 }  // namespace lbmnn
@@ -342,6 +351,7 @@ struct lbm_nn_ctx {
   float* y = nullptr;                   // network output planes [c_L][V]
   float* part = nullptr;                // weight-gradient partials
   int chunk = 256;
+  int out_off = 0;                      // output c corrects / is compared with field out_off + c
   double* lpart = nullptr;              // loss partials
   float* fld = nullptr;                 // corrector staging: fields and correction (FP32)
   double* dfld = nullptr;               // FP64 fields / increments for lbm
@@ -579,6 +589,14 @@ int lbm_nn_set_scaling(lbm_nn n, const double* mean, const double* sd, const dou
   return LBM_OK;
 }
 
+int lbm_nn_set_output_offset(lbm_nn n, int offset) {
+  if (!n) return nn_fail(LBM_EINVAL, "lbm_nn_set_output_offset: NULL network");
+  if (offset < 0 || offset + n->ch[n->L] > n->ch[0])
+    return nn_fail(LBM_EINVAL, "lbm_nn_set_output_offset: offset + output channels must not exceed the input channels");
+  n->out_off = offset;
+  return LBM_OK;
+}
+
 int lbm_nn_forward(lbm_nn n, const float* x, float* y) {
   if (!n || !x || !y) return nn_fail(LBM_EINVAL, "lbm_nn_forward: NULL argument");
   int rc = nn_select(n);
@@ -591,13 +609,15 @@ int lbm_nn_forward(lbm_nn n, const float* x, float* y) {
 
 int lbm_nn_loss_backward(lbm_nn n, const float* x, const float* target, double* loss) {
   if (!n || !x || !target) return nn_fail(LBM_EINVAL, "lbm_nn_loss_backward: NULL argument");
-  if (n->ch[n->L] > n->ch[0]) return nn_fail(LBM_EINVAL, "lbm_nn_loss_backward: more outputs than inputs");
+  if (n->out_off + n->ch[n->L] > n->ch[0])
+    return nn_fail(LBM_EINVAL, "lbm_nn_loss_backward: output fields beyond the input fields");
   int rc = nn_select(n);
   if (rc) return rc;
   if ((rc = nn_forward(n, x))) return rc;
   const int V = n->V, C = n->ch[n->L];
   const int lblocks = (V + 255) / 256;
-  hipLaunchKernelGGL(lbmnn::loss_kernel, dim3(lblocks), dim3(256), 0, n->stream, n->y, x, target, n->inv_out_std, C, V,
+  hipLaunchKernelGGL(lbmnn::loss_kernel, dim3(lblocks), dim3(256), 0, n->stream, n->y, x, target, n->inv_out_std, C,
+                     n->out_off, V,
                      n->dA, n->lpart);
   NN_HIP(hipGetLastError(), "loss kernel");
   // dA holds the gradient with respect to the output of layer l (pre-ReLU for l < L-1)
@@ -669,8 +689,8 @@ int lbm_nn_fields_to_planes(int D, int64_t nodes, const double* rho, const doubl
 int lbm_nn_correct(lbm_nn n, lbm_handle h) {
   if (!n || !h) return nn_fail(LBM_EINVAL, "lbm_nn_correct: NULL argument");
   const int D = h->lattice;
-  if (n->ch[0] != D + 2 || n->ch[n->L] != D + 2)
-    return nn_fail(LBM_EINVAL, "lbm_nn_correct: the network must map D + 2 fields to D + 2 corrections");
+  if (n->ch[0] != D + 2 || n->out_off + n->ch[n->L] > D + 2)
+    return nn_fail(LBM_EINVAL, "lbm_nn_correct: the network must read the D + 2 fields and correct fields among them");
   if (h->n[0] != n->g.nx || h->n[1] != n->g.ny || h->n[2] != n->g.nz)
     return nn_fail(LBM_EINVAL, "lbm_nn_correct: grid of the handle differs from the network's");
   int rc = nn_select(n);
@@ -693,7 +713,7 @@ int lbm_nn_correct(lbm_nn n, lbm_handle h) {
     if (rc == LBM_OK) rc = nn_forward(n, n->fld);
     if (rc == LBM_OK) {
       hipLaunchKernelGGL(lbmnn::output_to_increments_kernel, dim3((V + 255) / 256), dim3(256), 0, n->stream, n->y,
-                         n->out_std, D, V, drho, du, dT);
+                         n->out_std, n->ch[n->L], n->out_off, D, V, drho, du, dT);
       e = hipGetLastError();
       if (e != hipSuccess) rc = nn_hip(e, "increments kernel");
     }

@@ -97,6 +97,7 @@ def _load():
     L.lbm_nn_loss_backward.argtypes = [vp, vp, vp, dp]
     L.lbm_nn_adam_step.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, i64]
     L.lbm_nn_correct.argtypes = [vp, vp]
+    L.lbm_nn_set_output_offset.argtypes = [vp, C.c_int]
     L.lbm_nn_fields_to_planes.argtypes = [C.c_int, i64, vp, vp, vp, vp, vp]
     L.lbm_fields_set.argtypes = [vp, vp, vp, vp, C.c_int]
     L.lbm_batch_create.argtypes = [C.POINTER(vp), C.POINTER(vp), C.c_int]
@@ -112,7 +113,8 @@ def _load():
                  "lbm_batch_tune", "lbm_batch_step", "lbm_fields_add", "lbm_filter_moments", "lbm_nn_create",
                  "lbm_nn_destroy", "lbm_nn_set_stream", "lbm_nn_set_params", "lbm_nn_get_params", "lbm_nn_get_grads",
                  "lbm_nn_zero_grad", "lbm_nn_set_scaling", "lbm_nn_forward", "lbm_nn_loss_backward",
-                 "lbm_nn_adam_step", "lbm_nn_correct", "lbm_nn_fields_to_planes", "lbm_fields_set"):
+                 "lbm_nn_adam_step", "lbm_nn_correct", "lbm_nn_fields_to_planes", "lbm_fields_set",
+                 "lbm_nn_set_output_offset"):
         getattr(L, name).restype = C.c_int
     return L
 
@@ -406,6 +408,10 @@ def lbm_nn_set_scaling(n, mean, std, out_std=None) -> int:
     dp = C.POINTER(C.c_double)
     return _check(_L.lbm_nn_set_scaling(n, m.ctypes.data_as(dp), s.ctypes.data_as(dp),
                                         None if o is None else o.ctypes.data_as(dp)))
+
+
+def lbm_nn_set_output_offset(n, offset: int) -> int:
+    return _check(_L.lbm_nn_set_output_offset(n, int(offset)))
 
 
 def lbm_nn_forward(n, x, y) -> int:

@@ -275,3 +275,49 @@ def test_correct_adds_the_network_output():
     assert np.abs(after[1] - (before[1] + OUT[1:4, None, None, None] * y[1:4])).max() < 1e-6
     assert np.abs(after[2] - (before[2] + OUT[4] * y[4])).max() < 1e-7
     assert np.abs(y).max() > 1e-3 and np.abs(OUT[4] * y[4]).max() > 1e-6  # not trivially zero
+
+
+def test_velocity_only_network_loss_gradients_and_correction():
+    """A 5 -> 3 network with output offset 1 (it corrects u only): loss and
+    gradients against the bf16-storage reference, and lbm_nn_correct leaves
+    rho and T unchanged."""
+    lbm = _lbm()
+    ch = [5, 32, 32, 3]
+    shape = (4, 8, 32)
+    p = _params(15, channels=ch)
+    x = _fields(shape, 16)
+    t = x + 0.3 * OUT[:, None, None, None] * np.random.default_rng(17).normal(size=x.shape)
+    x, t = (a.astype(np.float32).astype(np.float64) for a in (x, t))
+    n = lbm.lbm_nn_create(ch, shape[::-1])
+    try:
+        lbm.lbm_nn_set_params(n, p.astype(np.float32))
+        lbm.lbm_nn_set_scaling(n, MEAN, STD, OUT[1:4])
+        lbm.lbm_nn_set_output_offset(n, 1)
+        lbm.lbm_nn_zero_grad(n)
+        loss = lbm.lbm_nn_loss_backward(n, torch.from_numpy(x.astype(np.float32)).cuda(),
+                                        torch.from_numpy(t.astype(np.float32)).cuda())
+        g = lbm.lbm_nn_get_grads(n).astype(np.float64)
+        l16, g16 = N.loss_and_grad(p, ch, x, t, MEAN, STD, store=N.bf16, out_std=OUT[1:4], out_offset=1)
+        print(f"  loss {loss:.6e} reference {l16:.6e}", flush=True)
+        assert loss == pytest.approx(l16, rel=1e-4)
+        assert float(g @ g16 / (np.linalg.norm(g) * np.linalg.norm(g16))) > 0.99999
+        with pytest.raises(lbm.LbmError):
+            lbm.lbm_nn_set_output_offset(n, 3)  # 3 + 3 outputs > 5 fields
+        dims = shape[::-1]
+        rho, u, T = I.smooth_random(3, dims, seed=18, u_amp=0.05)
+        h = lbm.lbm_create(3, dims, 1.4, 0.7, 0.02, precision=lbm.LBM_FP32_DEV, visc_exponent=0.76, T_ref=0.15)
+        try:
+            lbm.lbm_init_fields(h, rho, u, T)
+            lbm.lbm_step(h, 2)
+            before = [np.zeros(a.shape) for a in (rho, u, T)]
+            lbm.lbm_moments(h, *before)
+            lbm.lbm_nn_correct(n, h)
+            after = [np.zeros(a.shape) for a in (rho, u, T)]
+            lbm.lbm_moments(h, *after)
+        finally:
+            lbm.lbm_destroy(h)
+    finally:
+        lbm.lbm_nn_destroy(n)
+    assert np.abs(after[0] - before[0]).max() < 1e-6
+    assert np.abs(after[2] - before[2]).max() < 1e-7
+    assert np.abs(after[1] - before[1]).max() > 1e-5

@@ -38,14 +38,14 @@ def test_translation_equivariance():
     assert np.allclose(ys, np.roll(y, (1, -2, 3), axis=(1, 2, 3)), atol=1e-13)
 
 
-def test_gradients_match_finite_differences():
-    ch = [3, 32, 32, 3]
+@pytest.mark.parametrize("ch,offset", [([3, 32, 32, 3], 0), ([3, 32, 32, 2], 1)])
+def test_gradients_match_finite_differences(ch, offset):
     p = _rand_params(ch, 4, scale=0.15)
     r = np.random.default_rng(5)
     x = 1.0 + 0.1 * r.normal(size=(3, 4, 4, 5))
     t = x + 0.05 * r.normal(size=x.shape)
     mean, std = np.array([1.0, 0.9, 1.1]), np.array([0.1, 0.2, 0.15])
-    loss, g = N.loss_and_grad(p, ch, x, t, mean, std)
+    loss, g = N.loss_and_grad(p, ch, x, t, mean, std, out_offset=offset)
     assert loss > 0
     idx = r.choice(p.size, 60, replace=False)
     eps = 1e-6
@@ -53,7 +53,8 @@ def test_gradients_match_finite_differences():
         pp, pm = p.copy(), p.copy()
         pp[k] += eps
         pm[k] -= eps
-        fd = (N.loss_and_grad(pp, ch, x, t, mean, std)[0] - N.loss_and_grad(pm, ch, x, t, mean, std)[0]) / (2 * eps)
+        fd = (N.loss_and_grad(pp, ch, x, t, mean, std, out_offset=offset)[0]
+              - N.loss_and_grad(pm, ch, x, t, mean, std, out_offset=offset)[0]) / (2 * eps)
         assert fd == pytest.approx(g[k], rel=1e-5, abs=1e-9 * max(1.0, abs(loss)))
 
 
@@ -134,3 +135,20 @@ def test_bf16_storage_changes_the_network_by_its_rounding_only():
     q = N.bf16(_rand_params(one, 12))
     xi = N.bf16(r.normal(size=(2, 3, 4, 5)))
     assert np.array_equal(N.forward(q, one, xi, store=N.bf16)[0], N.forward(q, one, xi)[0])
+
+
+def test_output_offset_compares_the_named_fields():
+    """With offset 1 the outputs are compared with fields 1 and 2: changing the
+    target of field 0 changes nothing, changing field 1's does."""
+    ch = [3, 32, 2]
+    p = _rand_params(ch, 13)
+    r = np.random.default_rng(14)
+    x = 1.0 + 0.1 * r.normal(size=(3, 4, 4, 4))
+    t = x + 0.05 * r.normal(size=x.shape)
+    mean, std = np.ones(3), np.full(3, 0.1)
+    l0 = N.loss_and_grad(p, ch, x, t, mean, std, out_offset=1)[0]
+    t2 = t.copy()
+    t2[0] += 1.0
+    assert N.loss_and_grad(p, ch, x, t2, mean, std, out_offset=1)[0] == l0
+    t2[1] += 0.01
+    assert N.loss_and_grad(p, ch, x, t2, mean, std, out_offset=1)[0] != l0
