@@ -184,6 +184,7 @@ def generate_pairs(w: Workload, seeds, Ma_ts, log=print):
                                       gamma=w.gamma)
         fine = make_handle(w, w.n_fine, Ma)
         coarse = make_handle(w, nc, Ma)
+        ok = True
         try:
             lbm.lbm_init_fields(fine, rho, u, T)
             del rho, u, T
@@ -196,8 +197,10 @@ def generate_pairs(w: Workload, seeds, Ma_ts, log=print):
                 lbm.lbm_moments(coarse, cr, cu, cT)
                 lbm.lbm_nn_fields_to_planes(3, cr, cu, cT, pairs[used + k, 0])
                 lbm.lbm_nn_fields_to_planes(3, fr, fu, fT, pairs[used + k, 1])
-                lbm.lbm_fields_set(coarse, fr, fu, fT)
+                lbm.lbm_fields_set(coarse, fr, fu, fT)  # refuses a bad filtered field
             ok = _healthy(fine) and _healthy(coarse)
+        except lbm.LbmError:  # the fine run left the method's stable range
+            ok = False
         finally:
             lbm.lbm_destroy(fine)
             lbm.lbm_destroy(coarse)
@@ -342,9 +345,16 @@ def _timed_final(w, n, Ma, init, steps, net=None, every=None, reps=3):
             best = min(best, run(w, h, steps, net, every))
         ok = _healthy(h)
         fields = _host_fields(h, n)
+    except lbm.LbmError:  # a correction met a bad node: the run left the stable range
+        ok = False
+        fields = tuple(np.full(s, np.nan) for s in ((n,) * 3, (3,) + (n,) * 3, (n,) * 3))
     finally:
         lbm.lbm_destroy(h)
     return fields, best, ok
+
+
+def _error(u, E_ref, kmax, ok):
+    return spectrum_error(spectrum(u), E_ref, kmax) if ok else float("inf")
 
 
 def evaluate(w: Workload, net, seeds, Ma_ts, grids=None, log=print):
@@ -372,19 +382,22 @@ def evaluate(w: Workload, net, seeds, Ma_ts, grids=None, log=print):
             fine_ok = _healthy(fine)
         finally:
             lbm.lbm_destroy(fine)
+        if not fine_ok:
+            log(f"[eval] seed {seed} Ma_t {Ma:.3f}: the fine run left the stable range; seed skipped")
+            continue
         E_ref = spectrum(ref[1])
         row = {"seed": seed, "Ma_t": Ma, "fine_ok": fine_ok}
         (_, u_l, _), t_l, ok_l = _timed_final(w, nc, Ma, init_c, w.coarse_steps, net, w.every)
-        row["learned"] = {"error": spectrum_error(spectrum(u_l), E_ref, kmax), "seconds": t_l, "ok": ok_l}
+        row["learned"] = {"error": _error(u_l, E_ref, kmax, ok_l), "seconds": t_l, "ok": ok_l}
         plain = []
         for n in grids:
             steps = w.coarse_steps * n // nc
             init = init_c if n == nc else remap(rho, u, T, n, w.Cv)
             (r_p, u_p, T_p), t_p, ok_p = _timed_final(w, n, Ma, init, steps)
-            if n != nc:
+            if n != nc and ok_p:
                 r_p, u_p, T_p = remap(r_p, u_p, T_p, nc, w.Cv)
-            plain.append({"n": n, "steps": steps, "error": spectrum_error(spectrum(u_p), E_ref, kmax),
-                          "seconds": t_p, "ok": ok_p})
+            plain.append({"n": n, "steps": steps, "error": _error(u_p, E_ref, kmax, ok_p), "seconds": t_p,
+                          "ok": ok_p})
         row["plain"] = plain
         fit = [p for p in plain if p["seconds"] <= t_l]
         row["plain_coarse"] = plain[0]
