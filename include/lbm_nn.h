@@ -61,6 +61,9 @@ int lbm_nn_set_scaling(lbm_nn net, const double* mean, const double* std, const 
    correction); offset + c[L] <= c[0].  Default 0.  E.g. offset 1 with
    c[L] = D: the network corrects the velocity only. */
 int lbm_nn_set_output_offset(lbm_nn net, int offset);
+/* lbm_nn_correct clips each normalised output to [-limit, limit] (so an
+   increment is at most limit out_std_c); 0 (default) clips nothing. */
+int lbm_nn_set_correction_limit(lbm_nn net, double limit);
 /* y = network(normalised x): x is c[0] planes, y is c[L] planes (device). */
 int lbm_nn_forward(lbm_nn net, const float* x, float* y);
 /* Training loss of one sample and its gradients (accumulated):

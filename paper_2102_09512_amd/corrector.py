@@ -6,7 +6,10 @@ A coarse run of the method (n_c^3) is corrected every few steps by a small
 The network reads rho, u and T and corrects u: trained on all five fields,
 the density and temperature corrections lower the pointwise error of those
 fields but damp the small-scale velocity, so the kinetic-energy spectrum gets
-worse; the velocity-only corrector improves both.
+worse; the velocity-only corrector improves both.  Each correction is clipped
+to two standard deviations of the training corrections: near the method's
+stability limit (early acoustic transients at Ma_t ~ 0.5 on the coarse grid)
+a rare large correction can otherwise tip a run over.
 The corrector is not part of the paper; its training data come from the
 method's own fine runs, and the fine run stays the judge of its error.
 
@@ -64,6 +67,7 @@ class Workload:
     windows: int = 32  # corrections per run
     channels: tuple = (5, 32, 32, 32, 3)  # reads rho, u, T; corrects u
     out_offset: int = 1  # output c corrects field out_offset + c
+    limit: float = 2.0  # corrections clipped to 2 standard deviations of the training corrections
 
     @property
     def factor(self) -> int:
@@ -269,6 +273,7 @@ def train(w: Workload, pairs, epochs=20, lr=1e-3, batch=4, seed=0, log=print) ->
         mean, std, out = scaling_from(pairs, out_fields(w), seed=seed)
         lbm.lbm_nn_set_scaling(net, mean, std, out)
         lbm.lbm_nn_set_output_offset(net, w.out_offset)
+        lbm.lbm_nn_set_correction_limit(net, w.limit)
         rng = np.random.default_rng(seed)
         P = pairs.shape[0]
         steps_per_epoch = (P + batch - 1) // batch

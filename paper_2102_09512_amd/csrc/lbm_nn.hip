@@ -290,16 +290,19 @@ __global__ void __launch_bounds__(256) fields_to_input_kernel(const double* __re
 
 // normalised correction planes -> FP64 increments drho[V], du[D V], dT[V]:
 // output c corrects field off + c (0 rho, 1..D u, D + 1 T); fields without an
-// output get a zero increment
+// output get a zero increment; with limit > 0 the normalised output is
+// clipped to [-limit, limit] first
 __global__ void __launch_bounds__(256) output_to_increments_kernel(const float* __restrict__ y,
                                                                    const float* __restrict__ sd, int C, int off, int D,
-                                                                   int V, double* __restrict__ drho,
+                                                                   float limit, int V, double* __restrict__ drho,
                                                                    double* __restrict__ du, double* __restrict__ dT) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
   for (int fld = 0; fld < D + 2; ++fld) {
     const int c = fld - off;
-    const double inc = (c >= 0 && c < C) ? (double)y[(size_t)c * V + v] * sd[c] : 0.0;
+    float yc = (c >= 0 && c < C) ? y[(size_t)c * V + v] : 0.f;
+    if (limit > 0.f) yc = fminf(fmaxf(yc, -limit), limit);
+    const double inc = (c >= 0 && c < C) ? (double)yc * sd[c] : 0.0;
     if (fld == 0) drho[v] = inc;
     else if (fld <= D) du[(size_t)(fld - 1) * V + v] = inc;
     else dT[v] = inc;
@@ -352,6 +355,7 @@ struct lbm_nn_ctx {
   float* part = nullptr;                // weight-gradient partials
   int chunk = 256;
   int out_off = 0;                      // output c corrects / is compared with field out_off + c
+  double limit = 0.0;                   // lbm_nn_correct clips outputs to [-limit, limit] (0: no clip)
   double* lpart = nullptr;              // loss partials
   float* fld = nullptr;                 // corrector staging: fields and correction (FP32)
   double* dfld = nullptr;               // FP64 fields / increments for lbm
@@ -597,6 +601,14 @@ int lbm_nn_set_output_offset(lbm_nn n, int offset) {
   return LBM_OK;
 }
 
+int lbm_nn_set_correction_limit(lbm_nn n, double limit) {
+  if (!n) return nn_fail(LBM_EINVAL, "lbm_nn_set_correction_limit: NULL network");
+  if (!(limit >= 0.0) || !std::isfinite(limit))
+    return nn_fail(LBM_EINVAL, "lbm_nn_set_correction_limit: limit must be finite and >= 0");
+  n->limit = limit;
+  return LBM_OK;
+}
+
 int lbm_nn_forward(lbm_nn n, const float* x, float* y) {
   if (!n || !x || !y) return nn_fail(LBM_EINVAL, "lbm_nn_forward: NULL argument");
   int rc = nn_select(n);
@@ -713,7 +725,7 @@ int lbm_nn_correct(lbm_nn n, lbm_handle h) {
     if (rc == LBM_OK) rc = nn_forward(n, n->fld);
     if (rc == LBM_OK) {
       hipLaunchKernelGGL(lbmnn::output_to_increments_kernel, dim3((V + 255) / 256), dim3(256), 0, n->stream, n->y,
-                         n->out_std, n->ch[n->L], n->out_off, D, V, drho, du, dT);
+                         n->out_std, n->ch[n->L], n->out_off, D, (float)n->limit, V, drho, du, dT);
       e = hipGetLastError();
       if (e != hipSuccess) rc = nn_hip(e, "increments kernel");
     }

@@ -98,6 +98,7 @@ def _load():
     L.lbm_nn_adam_step.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, i64]
     L.lbm_nn_correct.argtypes = [vp, vp]
     L.lbm_nn_set_output_offset.argtypes = [vp, C.c_int]
+    L.lbm_nn_set_correction_limit.argtypes = [vp, C.c_double]
     L.lbm_nn_fields_to_planes.argtypes = [C.c_int, i64, vp, vp, vp, vp, vp]
     L.lbm_fields_set.argtypes = [vp, vp, vp, vp, C.c_int]
     L.lbm_batch_create.argtypes = [C.POINTER(vp), C.POINTER(vp), C.c_int]
@@ -114,7 +115,7 @@ def _load():
                  "lbm_nn_destroy", "lbm_nn_set_stream", "lbm_nn_set_params", "lbm_nn_get_params", "lbm_nn_get_grads",
                  "lbm_nn_zero_grad", "lbm_nn_set_scaling", "lbm_nn_forward", "lbm_nn_loss_backward",
                  "lbm_nn_adam_step", "lbm_nn_correct", "lbm_nn_fields_to_planes", "lbm_fields_set",
-                 "lbm_nn_set_output_offset"):
+                 "lbm_nn_set_output_offset", "lbm_nn_set_correction_limit"):
         getattr(L, name).restype = C.c_int
     return L
 
@@ -412,6 +413,10 @@ def lbm_nn_set_scaling(n, mean, std, out_std=None) -> int:
 
 def lbm_nn_set_output_offset(n, offset: int) -> int:
     return _check(_L.lbm_nn_set_output_offset(n, int(offset)))
+
+
+def lbm_nn_set_correction_limit(n, limit: float) -> int:
+    return _check(_L.lbm_nn_set_correction_limit(n, float(limit)))
 
 
 def lbm_nn_forward(n, x, y) -> int:
