@@ -198,7 +198,8 @@ int lbm_create(lbm_handle* out, int lattice, const int64_t dims[3], double gamma
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(opt.u_ref[a]) || std::fabs(opt.u_ref[a]) >= 1.0)
       return fail(LBM_EINVAL, "lbm_create: u_ref components must be finite and |u_ref| < 1");
-  if (opt.cv_poly[0] != 0.0 || opt.cv_poly[1] != 0.0 || opt.cv_poly[2] != 0.0)
+  const bool caloric = opt.cv_poly[0] != 0.0 || opt.cv_poly[1] != 0.0 || opt.cv_poly[2] != 0.0;
+  if (caloric)
     if (!(opt.cv_poly[0] > 0.0 && opt.cv_poly[1] >= 0.0 && opt.cv_poly[2] >= 0.0) ||
         !std::isfinite(opt.cv_poly[0] + opt.cv_poly[1] + opt.cv_poly[2]))
       return fail(LBM_EINVAL, "lbm_create: cv_poly needs cv_poly[0] > 0 and cv_poly[1], cv_poly[2] >= 0 (finite)");
@@ -210,7 +211,9 @@ int lbm_create(lbm_handle* out, int lattice, const int64_t dims[3], double gamma
     lbm::Tile t{opt.tile[0] ? opt.tile[0] : tile.bx, opt.tile[1] ? opt.tile[1] : tile.by,
                 opt.tile[2] ? opt.tile[2] : tile.chunk};
     if (lattice == LBM_D2Q9 && !opt.tile[1]) t.by = 1;
-    if (!lbm::tile_supported(lattice, opt.precision, t) || t.chunk < 1) return fail(LBM_EINVAL, "lbm_create: launch tile not available");
+    if (!lbm::tile_supported(lattice, opt.precision, t, caloric) || t.chunk < 1)
+      return fail(LBM_EINVAL, caloric ? "lbm_create: with cv_poly only the default launch shape is compiled"
+                                      : "lbm_create: launch tile not available");
     tile = t;
   }
 
@@ -616,6 +619,8 @@ int lbm_batch_create(lbm_batch* out, const lbm_handle* boxes, int count) {
     if (boxes[i]->lattice != boxes[0]->lattice || boxes[i]->precision != boxes[0]->precision ||
         boxes[i]->device != boxes[0]->device)
       return fail(LBM_EINVAL, "lbm_batch_create: handles differ in lattice, precision or device");
+    if (boxes[i]->sp.caloric)
+      return fail(LBM_EINVAL, "lbm_batch_create: handles with a general caloric law (cv_poly) are not batched");
     for (int j = 0; j < i; ++j)
       if (boxes[j] == boxes[i]) return fail(LBM_EINVAL, "lbm_batch_create: a handle appears twice");
   }

@@ -205,8 +205,10 @@ __device__ inline NodeMoments<R> pulled_moments_batched(const __amdgpu_buffer_rs
 }
 
 // One work-group's share of a step: tile lb (x fastest, then y, then the
-// march chunk) of the box described by p.
-template <int D, bool DEV, typename S, int BX, int BY>
+// march chunk) of the box described by p.  CAL: the general caloric law
+// (p.caloric must equal CAL); with CAL false the constant-C_v arithmetic is
+// all the kernel contains.
+template <int D, bool DEV, typename S, int BX, int BY, bool CAL = false>
 __device__ inline void step_tile(const S* __restrict__ src, S* __restrict__ dst, const StepParams& p, int lb) {
   using R = typename StoreOf<S>::R;
   constexpr int Q = lat_q(D);
@@ -216,7 +218,9 @@ __device__ inline void step_tile(const S* __restrict__ src, S* __restrict__ dst,
   __shared__ R lq0[2][BY][BX + 2];                    // anomaly along in-plane axis 0 (x)
   __shared__ R lq1[2][(D == 3) ? BY + 2 : 1][BX];     // anomaly along in-plane axis 1 (y, D3Q27 only)
 
-  const NodeConsts k = node_consts(p);
+  NodeConsts k = node_consts(p);
+  k.caloric = CAL ? 1 : 0;
+  if constexpr (!CAL) k.U0 = k.Cv * k.T0;  // the same value, formed from constants already held
 
   const int tx = lb % p.tiles_x;
   const int rest = lb / p.tiles_x;
@@ -437,10 +441,10 @@ __device__ inline int xcd_logical_block(int b, int nblocks) {
   return xcd * q8 + min(xcd, r8) + (b >> 3);
 }
 
-template <int D, bool DEV, typename S, int BX, int BY>
+template <int D, bool DEV, typename S, int BX, int BY, bool CAL = false>
 __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src, S* __restrict__ dst,
                                                       const StepParams p) {
-  step_tile<D, DEV, S, BX, BY>(src, dst, p, xcd_logical_block(blockIdx.x, p.nblocks));
+  step_tile<D, DEV, S, BX, BY, CAL>(src, dst, p, xcd_logical_block(blockIdx.x, p.nblocks));
 }
 
 // Several boxes in one launch: logical block g belongs to the last box whose
@@ -687,9 +691,9 @@ __global__ void __launch_bounds__(256) unpack_kernel(const S* __restrict__ state
 // Launchers
 // ---------------------------------------------------------------------------
 
-template <int D, bool DEV, typename S, int BX, int BY>
+template <int D, bool DEV, typename S, int BX, int BY, bool CAL = false>
 static hipError_t launch_step_t(const Ctx& c, const void* src, void* dst) {
-  hipLaunchKernelGGL((step_kernel<D, DEV, S, BX, BY>), dim3(c.sp.nblocks), dim3(BX * BY), 0, c.stream,
+  hipLaunchKernelGGL((step_kernel<D, DEV, S, BX, BY, CAL>), dim3(c.sp.nblocks), dim3(BX * BY), 0, c.stream,
                      static_cast<const S*>(src), static_cast<S*>(dst), c.sp);
   return hipGetLastError();
 }
@@ -714,8 +718,9 @@ Tile default_tile(int D, int precision, const int64_t n[3]) {
   return Tile{128, 1, (int)(chunk < n[1] ? chunk : n[1])};
 }
 
-bool tile_supported(int D, int precision, const Tile& t) {
+bool tile_supported(int D, int precision, const Tile& t, bool caloric) {
   (void)precision;
+  if (caloric) return D == 3 ? (t.bx == 64 && t.by == 4) : (t.bx == 128 && t.by == 1);
   if (D == 3) return (t.bx == 64 && (t.by == 4 || t.by == 8)) || (t.bx == 32 && t.by == 8);
   return t.by == 1 && (t.bx == 64 || t.bx == 128 || t.bx == 256);
 }
@@ -723,6 +728,14 @@ bool tile_supported(int D, int precision, const Tile& t) {
 template <int D, bool DEV, typename S>
 static hipError_t dispatch_tile(const Ctx& c, const void* src, void* dst) {
   const Tile& t = c.tile;
+  if (c.sp.caloric) {  // the general caloric law: the default shape only
+    if constexpr (D == 3) {
+      if (t.bx == 64 && t.by == 4) return launch_step_t<D, DEV, S, 64, 4, true>(c, src, dst);
+    } else {
+      if (t.bx == 128) return launch_step_t<D, DEV, S, 128, 1, true>(c, src, dst);
+    }
+    return hipErrorInvalidValue;
+  }
   if constexpr (D == 3) {
     if (t.bx == 64 && t.by == 4) return launch_step_t<D, DEV, S, 64, 4>(c, src, dst);
     if (t.bx == 64 && t.by == 8) return launch_step_t<D, DEV, S, 64, 8>(c, src, dst);

@@ -66,6 +66,9 @@ def test_create_rejects_bad_arguments(lbm, args, needle):
     (dict(deriv_scheme=3), "derivative"),
     (dict(T_ref=0.0), "T_ref"),
     (dict(rho_ref=-1.0), "rho_ref"),
+    (dict(cv_poly=(0.0, 1.0, 0.0)), "cv_poly"),
+    (dict(cv_poly=(1.5, -1.0, 0.0)), "cv_poly"),
+    (dict(cv_poly=(1.5, 5.0, 20.0), tile=(64, 8, 16)), "default launch shape"),
     (dict(tile=(48, 4, 8)), "tile"),
     (dict(u_ref=(1.5, 0.0, 0.0)), "u_ref"),
     (dict(u_ref=(0.0, float("nan"), 0.0)), "u_ref"),

@@ -524,3 +524,17 @@ def test_filter_with_general_caloric_law():
     assert np.abs(out[0] - rc).max() <= 1e-14
     assert np.abs(out[1] - uc).max() <= 1e-14
     assert np.abs(U(out[2]) - e).max() <= 1e-14 * np.abs(e).max()
+
+
+def test_batch_refuses_a_general_caloric_law():
+    lbm = _lbm()
+    dims = (16, 8, 8)
+    hs = [lbm.lbm_create(3, dims, 1.4, 0.7, 0.02, precision=lbm.LBM_FP32_DEV, T_ref=0.15, cv_poly=cv)
+          for cv in (None, CV_LAW)]
+    try:
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_batch_create(hs)
+        assert "caloric" in str(e.value)
+    finally:
+        for h in hs:
+            lbm.lbm_destroy(h)
