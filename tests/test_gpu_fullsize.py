@@ -74,15 +74,27 @@ def _errs(out, ref):
 
 
 def test_shock_vortex_1024_full_field_fp64():
+    """FP64 within 1e-12 of the oracle at step 30; at step 100, as the vortex
+    passes the shock, the flow amplifies rounding-level differences about a
+    hundredfold, so the bar is the larger of 1e-12 and twice the case's FP64
+    conditioning floor: the departure of an oracle run whose initial fields
+    are perturbed by one unit in the last place."""
     n = 1024
     rho, u, T, _ = I.shock_vortex(n, n, r_v=32.0, x_s=512)
-    print("[gpu case] shock-vortex 1024^2 FP64, 100 steps", flush=True)
-    out = _sv_gpu((rho, u, T), [100], False, None)[0]
-    ref = _sv_oracle((rho, u, T), [100])[0]
-    errs = _errs(out, ref)
-    print("  field errors", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    for k, e in errs.items():
-        assert e <= 1e-12, (k, e)
+    print("[gpu case] shock-vortex 1024^2 FP64, steps 30 and 100", flush=True)
+    outs = _sv_gpu((rho, u, T), [30, 100], False, None)
+    refs = _sv_oracle((rho, u, T), [30, 100])
+    r = np.random.default_rng(0)
+    ulp = lambda a: a * (1 + 2.0 ** -52 * r.choice([-1.0, 1.0], size=a.shape))
+    floor = _errs(_sv_oracle((ulp(rho), ulp(u), ulp(T)), [100])[0], refs[1])
+    e30, e100 = _errs(outs[0], refs[0]), _errs(outs[1], refs[1])
+    print("  step 30 field errors", {k: f"{v:.2e}" for k, v in e30.items()}, flush=True)
+    print("  step 100 field errors", {k: f"{v:.2e}" for k, v in e100.items()},
+          "floor", {k: f"{v:.2e}" for k, v in floor.items()}, flush=True)
+    for k, e in e30.items():
+        assert e <= 1e-12, (30, k, e)
+    for k, e in e100.items():
+        assert e <= max(1e-12, 2.0 * floor[k]), (100, k, e, floor[k])
 
 
 def test_shock_vortex_1024_full_field_fp32():
