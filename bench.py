@@ -220,6 +220,7 @@ def run_learned(args, torch, lbm, dev):
     t0 = time.perf_counter()
     pairs = Cr.generate_pairs(w, *tr, log=_log)
     t_data = time.perf_counter() - t0
+    n_pairs = int(pairs.shape[0])
     res = Cr.train(w, pairs, epochs=args.steps, lr=args.lr, batch=4, log=_log)
     del pairs
     vp = Cr.generate_pairs(w, *ev, log=_log)
@@ -277,7 +278,7 @@ def run_learned(args, torch, lbm, dev):
                       "learned": [round(r["learned"]["error"], 5), round(1e3 * r["learned"]["seconds"], 2)],
                       "plain": [[p["n"], round(p["error"], 5), round(1e3 * p["seconds"], 2)] for p in r["plain"]]}
                      for r in rows],
-        "training": {"pairs": len(tr[0]) * w.windows, "data_seconds": round(t_data, 1),
+        "training": {"pairs": n_pairs, "seeds_used": n_pairs // w.windows, "data_seconds": round(t_data, 1),
                      "train_seconds": round(res.seconds, 1), "loss_first_epoch": round(res.history[0], 5),
                      "loss_last_epoch": round(res.history[-1], 5), "validation_loss": round(val_loss, 5),
                      "no_correction_loss": round(zero_loss, 5)},
