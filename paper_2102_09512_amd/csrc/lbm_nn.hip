@@ -60,10 +60,13 @@ __global__ void __launch_bounds__(256) pack_input_kernel(const float* __restrict
 }
 
 // Output tile of the convolution kernel: 32 nodes along x (the matrix-core
-// N dimension) times 4 rows along y times 4 planes along z; wave w computes
-// plane z0 + w.  The input tile with its one-node periodic halo is staged in
+// N dimension) times kTY rows along y times kTZ planes along z; row q of the
+// tile is (y0 + q % kTY, z0 + q / kTY) and wave w computes rows w kR ..
+// w kR + kR - 1.  The input tile with its one-node periodic halo is staged in
 // LDS once per block and read 27 times.
 constexpr int kTX = 32, kTY = 4, kTZ = 4;
+constexpr int kW = 8;                   // wavefronts per work-group
+constexpr int kR = kTY * kTZ / kW;      // output rows (32 nodes each) per wavefront
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
 
 // 16-byte chunk c of the node at halo column hx is stored at chunk
@@ -84,7 +87,7 @@ __device__ inline int swizzle(int c, int hx) {
 // produced it).  bias may be null; it holds cout values.
 // Requires nx % 32 == 0, ny % 4 == 0, nz % 4 == 0; grid = tiles.
 template <int CIN, bool OUT_PLANAR>
-__global__ void __launch_bounds__(256) conv_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ wp,
+__global__ void __launch_bounds__(64 * kW) conv_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ wp,
                                                    const float* __restrict__ bias, int relu,
                                                    const __bf16* __restrict__ mask, void* __restrict__ out, int cout,
                                                    const Grid g, int V) {
@@ -93,7 +96,7 @@ __global__ void __launch_bounds__(256) conv_kernel(const __bf16* __restrict__ in
   const int tx = g.nx / kTX, ty = g.ny / kTY;
   const int b = blockIdx.x;
   const int x0 = (b % tx) * kTX, y0 = ((b / tx) % ty) * kTY, z0 = (b / (tx * ty)) * kTZ;
-  for (int e = threadIdx.x; e < kHZ * kHY * kHX * CH; e += 256) {
+  for (int e = threadIdx.x; e < kHZ * kHY * kHX * CH; e += 64 * kW) {
     const int c = e % CH, node = e / CH;
     const int hx = node % kHX, hy = (node / kHX) % kHY, hz = node / (kHX * kHY);
     const int gx = wrap(x0 + hx - 1, g.nx), gy = wrap(y0 + hy - 1, g.ny), gz = wrap(z0 + hz - 1, g.nz);
@@ -103,19 +106,20 @@ __global__ void __launch_bounds__(256) conv_kernel(const __bf16* __restrict__ in
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r = lane & 31, half = lane >> 5;
-  f16v acc[kTY] = {};
+  f16v acc[kR] = {};
 #pragma unroll 1
   for (int t = 0; t < 27; ++t) {
     const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
     const int hx = r + dx + 1;
-    const __bf16* row0 = tile + ((w + dz + 1) * kHY + dy + 1) * kHX * CIN + hx * CIN;
+    const __bf16* col = tile + hx * CIN;
 #pragma unroll
     for (int cc = 0; cc < CIN / 16; ++cc) {
       const bf8 a = *(const bf8*)(wp + ((size_t)(t * (CIN / 16) + cc) * 32 + r) * 16 + 8 * half);
       const int off = swizzle<CIN>(2 * cc + half, hx) * 8;
 #pragma unroll
-      for (int j = 0; j < kTY; ++j) {
-        const bf8 bv = *(const bf8*)(row0 + j * kHX * CIN + off);
+      for (int j = 0; j < kR; ++j) {
+        const int q = w * kR + j, hy = q % kTY + dy + 1, hz = q / kTY + dz + 1;
+        const bf8 bv = *(const bf8*)(col + (hz * kHY + hy) * kHX * CIN + off);
         acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[j], 0, 0, 0);
       }
     }
@@ -127,8 +131,9 @@ __global__ void __launch_bounds__(256) conv_kernel(const __bf16* __restrict__ in
     bo[i] = bias && c < cout ? bias[c] : 0.f;
   }
 #pragma unroll
-  for (int j = 0; j < kTY; ++j) {
-    const int v = (x0 + r) + g.nx * ((y0 + j) + g.ny * (z0 + w));
+  for (int j = 0; j < kR; ++j) {
+    const int q = w * kR + j;
+    const int v = (x0 + r) + g.nx * ((y0 + q % kTY) + g.ny * (z0 + q / kTY));
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int c0 = 8 * q + 4 * half;
@@ -160,58 +165,117 @@ __global__ void __launch_bounds__(256) conv_kernel(const __bf16* __restrict__ in
   }
 }
 
-// Partial weight gradients: part[task][i][o] = sum over the chunk's nodes v of
-// in[shift(v, t)][i] dout[v][o], task = t * nchunks + chunk (rows i >= CIN zero).
+// Weight and bias gradients of one layer, per work-group partial sums:
+//   slot t < 27: part[t][b][i][o] = sum over the group's nodes v of in[v + s_t][i] dout[v][o]
+//   slot 27:     part[27][b][i][o] = sum over the group's nodes v of dout[v][o] (every row i)
+// (the bias gradient as the product with a row of ones).  Work-group b takes
+// tiles b tpb .. b tpb + tpb - 1 of 32 x 4 x 2 nodes (x fastest, then y, z).
+// Per tile the input with its one-node halo and the output gradient are
+// staged in LDS channel-major, so that the node index runs along the
+// matrix-core K dimension: lane (r, h) reads 8 consecutive nodes of channel r
+// as one 16-byte word.  The x offset of a tap is 0, 1 or 2 elements inside
+// two aligned words and is taken out with funnel shifts.  Wave w owns slots
+// w, w + 4, ..., w + 24 and keeps their sums in registers across the tiles.
+constexpr int kGX = 32, kGY = 4, kGZ = 2;
+constexpr int kGHY = kGY + 2, kGHZ = kGZ + 2, kGHX = kGX + 2;
+constexpr int kGRow = 40;                           // halo row: 34 nodes, padded to a 16-byte multiple
+constexpr int kGPlaneIn = kGHZ * kGHY * kGRow + 8;  // per channel; the 16 extra bytes spread the
+constexpr int kGPlaneD = kGZ * kGY * kGX + 8;       // channel planes over the LDS banks
+constexpr int kGMaxBlocks = 512;
+
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
 template <int CIN>
 __global__ void __launch_bounds__(256) wgrad_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ dout,
-                                                    float* __restrict__ part, const Grid g, int V, int chunk) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nchunks = V / chunk;
-  const int task = blockIdx.x * 4 + wave;
-  if (task >= 27 * nchunks) return;
-  const int t = task / nchunks, ch = task % nchunks;
+                                                    float* __restrict__ part, const Grid g, int ntiles, int tpb) {
+  __shared__ __attribute__((aligned(16))) __bf16 inT[CIN * kGPlaneIn];
+  __shared__ __attribute__((aligned(16))) __bf16 dT[32 * kGPlaneD];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r = lane & 31, half = lane >> 5;
-  f16v acc = {};
-#pragma unroll 1
-  for (int vb = ch * chunk; vb < (ch + 1) * chunk; vb += 16) {
-    bf8 a, b;
+  const int tx = g.nx / kGX, ty = g.ny / kGY;
+  bf8 ones;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int v = vb + 8 * half + j;
-      a[j] = r < CIN ? in[(size_t)shifted(v, t, g) * CIN + r] : (__bf16)0.f;  // A[i = r][k = v]
-      b[j] = dout[(size_t)v * 32 + r];                                      // B[k = v][o = r]
+  for (int j = 0; j < 8; ++j) ones[j] = (__bf16)1.f;
+  f16v acc[7] = {};
+  const int first = blockIdx.x * tpb, last = min(first + tpb, ntiles);
+  for (int tile = first; tile < last; ++tile) {
+    const int x0 = (tile % tx) * kGX, y0 = ((tile / tx) % ty) * kGY, z0 = (tile / (tx * ty)) * kGZ;
+    __syncthreads();  // every wave is done with the previous tile
+    constexpr int NH = kGHX * kGHY * kGHZ;
+    for (int e = threadIdx.x; e < NH * (CIN / 8); e += 256) {
+      const int node = e % NH, c8 = e / NH;
+      const int hx = node % kGHX, hy = (node / kGHX) % kGHY, hz = node / (kGHX * kGHY);
+      const int gx = wrap(x0 + hx - 1, g.nx), gy = wrap(y0 + hy - 1, g.ny), gz = wrap(z0 + hz - 1, g.nz);
+      const bf8 val = *(const bf8*)(in + (size_t)(gx + g.nx * (gy + g.ny * gz)) * CIN + 8 * c8);
+      __bf16* dst = inT + 8 * c8 * kGPlaneIn + (hz * kGHY + hy) * kGRow + hx;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) dst[j * kGPlaneIn] = val[j];
     }
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-  }
-  float* dst = part + (size_t)task * 1024;
+    constexpr int ND = kGX * kGY * kGZ;
+    for (int e = threadIdx.x; e < ND * 4; e += 256) {
+      const int node = e % ND, c8 = e / ND;
+      const int xx = node % kGX, yy = (node / kGX) % kGY, zz = node / (kGX * kGY);
+      const bf8 val = *(const bf8*)(dout + (size_t)((x0 + xx) + g.nx * ((y0 + yy) + g.ny * (z0 + zz))) * 32 + 8 * c8);
+      __bf16* dst = dT + 8 * c8 * kGPlaneD + node;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) dst[(8 * (i >> 2) + 4 * half + (i & 3)) * 32 + r] = acc[i];
-}
-
-// grad[t][i][o] += sum_chunk part[t * nchunks + chunk][i][o] for i < cin, o < cout
-__global__ void __launch_bounds__(256) wgrad_reduce_kernel(const float* __restrict__ part, int nchunks, int cin, int cout,
-                                                           float* __restrict__ grad) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= 27 * cin * cout) return;
-  const int o = e % cout, i = (e / cout) % cin, t = e / (cout * cin);
-  float s = 0.f;
-  for (int c = 0; c < nchunks; ++c) s += part[((size_t)t * nchunks + c) * 1024 + i * 32 + o];
-  grad[e] += s;
-}
-
-// grad_b[o] += sum_v dout[v][o]: one block per output channel
-__global__ void __launch_bounds__(256) bgrad_kernel(const __bf16* __restrict__ dout, int V, float* __restrict__ grad_b) {
-  __shared__ float red[256];
-  const int o = blockIdx.x;
-  float s = 0.f;
-  for (int v = threadIdx.x; v < V; v += blockDim.x) s += (float)dout[(size_t)v * 32 + o];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      for (int j = 0; j < 8; ++j) dst[j * kGPlaneD] = val[j];
+    }
     __syncthreads();
+#pragma unroll 1
+    for (int row = 0; row < kGY * kGZ; ++row) {
+      const int yy = row % kGY, zz = row / kGY;
+#pragma unroll
+      for (int kb = 0; kb < kGX; kb += 16) {
+        // the output gradient of these 16 nodes serves all seven slots of the wave
+        const bf8 b = *(const bf8*)(dT + r * kGPlaneD + (zz * kGY + yy) * kGX + kb + 8 * half);
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+          const int t = w + 4 * k;  // 0..27: every slot exactly once over the four waves
+          const int o = t % 3, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;  // o = dx + 1
+          bf8 a;
+          if (t == 27) {
+            a = ones;
+          } else if (r < CIN) {
+            const __bf16* src = inT + r * kGPlaneIn + ((zz + dz + 1) * kGHY + yy + dy + 1) * kGRow + kb + 8 * half;
+            const u4 lo = *(const u4*)src, hi = *(const u4*)(src + 8);
+            u4 v;
+            if (o == 0) {
+              v = lo;
+            } else if (o == 2) {
+              v = u4{lo.y, lo.z, lo.w, hi.x};
+            } else {
+              v = u4{__builtin_amdgcn_alignbit(lo.y, lo.x, 16), __builtin_amdgcn_alignbit(lo.z, lo.y, 16),
+                     __builtin_amdgcn_alignbit(lo.w, lo.z, 16), __builtin_amdgcn_alignbit(hi.x, lo.w, 16)};
+            }
+            a = __builtin_bit_cast(bf8, v);
+          } else {
+            a = bf8{};
+          }
+          acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[k], 0, 0, 0);
+        }
+      }
+    }
   }
-  if (threadIdx.x == 0) grad_b[o] += red[0];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    float* dst = part + ((size_t)(w + 4 * k) * gridDim.x + blockIdx.x) * 1024;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) dst[(8 * (i >> 2) + 4 * half + (i & 3)) * 32 + r] = acc[k][i];
+  }
+}
+
+// grad[t][i][o] += sum_b part[t][b][i][o] (t < 27, i < cin, o < cout) and
+// grad_b[o] += sum_b part[27][b][0][o]; fixed summation order
+__global__ void __launch_bounds__(256) wgrad_reduce_kernel(const float* __restrict__ part, int nblk, int cin, int cout,
+                                                           float* __restrict__ grad, float* __restrict__ grad_b) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 28 * 1024) return;
+  const int t = e / 1024, i = (e / 32) % 32, o = e % 32;
+  if (o >= cout || (t < 27 && i >= cin) || (t == 27 && i != 0)) return;
+  float s = 0.f;
+  for (int b = 0; b < nblk; ++b) s += part[((size_t)t * nblk + b) * 1024 + i * 32 + o];
+  if (t < 27) grad[((size_t)t * cin + i) * cout + o] += s;
+  else grad_b[o] += s;
 }
 
 // r_c = y_c + (x_f - target_f) / out_std_c with f = off + c; loss partial sums
@@ -353,7 +417,6 @@ struct lbm_nn_ctx {
   __bf16 *dA = nullptr, *dB = nullptr;  // gradient ping-pong, bf16 [V][32]
   float* y = nullptr;                   // network output planes [c_L][V]
   float* part = nullptr;                // weight-gradient partials
-  int chunk = 256;
   int out_off = 0;                      // output c corrects / is compared with field out_off + c
   double limit = 0.0;                   // lbm_nn_correct clips outputs to [-limit, limit] (0: no clip)
   double* lpart = nullptr;              // loss partials
@@ -385,7 +448,8 @@ template <int CIN, bool PLANAR>
 hipError_t conv(lbm_nn n, const __bf16* in, const __bf16* w, const float* bias, int relu, const __bf16* mask,
                 void* out, int cout) {
   const int blocks = (n->g.nx / lbmnn::kTX) * (n->g.ny / lbmnn::kTY) * (n->g.nz / lbmnn::kTZ);
-  hipLaunchKernelGGL((lbmnn::conv_kernel<CIN, PLANAR>), dim3(blocks), dim3(256), 0, n->stream, in, w, bias, relu,
+  hipLaunchKernelGGL((lbmnn::conv_kernel<CIN, PLANAR>), dim3(blocks), dim3(64 * lbmnn::kW), 0, n->stream, in, w, bias,
+                     relu,
                      mask, out, cout, n->g, n->V);
   return hipGetLastError();
 }
@@ -470,8 +534,7 @@ int lbm_nn_create(lbm_nn* out, int layers, const int* channels, const int64_t di
   alloc((void**)&n->dA, sizeof(__bf16) * (size_t)V * 32);
   alloc((void**)&n->dB, sizeof(__bf16) * (size_t)V * 32);
   alloc((void**)&n->y, sizeof(float) * (size_t)V * 32);
-  n->chunk = 256;
-  alloc((void**)&n->part, sizeof(float) * 27 * (size_t)(V / n->chunk) * 1024);
+  alloc((void**)&n->part, sizeof(float) * 28 * (size_t)lbmnn::kGMaxBlocks * 1024);
   alloc((void**)&n->lpart, sizeof(double) * (size_t)((V + 255) / 256));
   alloc((void**)&n->fld, sizeof(float) * 2 * 16 * (size_t)V);
   alloc((void**)&n->dfld, sizeof(double) * 10 * (size_t)V);
@@ -634,23 +697,21 @@ int lbm_nn_loss_backward(lbm_nn n, const float* x, const float* target, double* 
   NN_HIP(hipGetLastError(), "loss kernel");
   // dA holds the gradient with respect to the output of layer l (pre-ReLU for l < L-1)
   __bf16 *dcur = n->dA, *dnext = n->dB;
-  const int nchunks = V / n->chunk;
+  const int ntiles = (n->g.nx / lbmnn::kGX) * (n->g.ny / lbmnn::kGY) * (n->g.nz / lbmnn::kGZ);
+  const int tpb = (ntiles + lbmnn::kGMaxBlocks - 1) / lbmnn::kGMaxBlocks;
+  const int nblk = (ntiles + tpb - 1) / tpb;
   for (int l = n->L - 1; l >= 0; --l) {
     const Layer& ly = n->layers[l];
-    const int wblocks = (27 * nchunks + 3) / 4;
     if (ly.cinp == 16)
-      hipLaunchKernelGGL((lbmnn::wgrad_kernel<16>), dim3(wblocks), dim3(256), 0, n->stream, n->act[l], dcur, n->part,
-                         n->g, V, n->chunk);
+      hipLaunchKernelGGL((lbmnn::wgrad_kernel<16>), dim3(nblk), dim3(256), 0, n->stream, n->act[l], dcur, n->part, n->g,
+                         ntiles, tpb);
     else
-      hipLaunchKernelGGL((lbmnn::wgrad_kernel<32>), dim3(wblocks), dim3(256), 0, n->stream, n->act[l], dcur, n->part,
-                         n->g, V, n->chunk);
+      hipLaunchKernelGGL((lbmnn::wgrad_kernel<32>), dim3(nblk), dim3(256), 0, n->stream, n->act[l], dcur, n->part, n->g,
+                         ntiles, tpb);
     NN_HIP(hipGetLastError(), "weight gradient kernel");
-    const int ne = 27 * ly.cin * ly.cout;
-    hipLaunchKernelGGL(lbmnn::wgrad_reduce_kernel, dim3((ne + 255) / 256), dim3(256), 0, n->stream, n->part, nchunks,
-                       ly.cin, ly.cout, n->grads + ly.w_off);
+    hipLaunchKernelGGL(lbmnn::wgrad_reduce_kernel, dim3(28 * 1024 / 256), dim3(256), 0, n->stream, n->part, nblk,
+                       ly.cin, ly.cout, n->grads + ly.w_off, n->grads + ly.b_off);
     NN_HIP(hipGetLastError(), "weight gradient reduction");
-    hipLaunchKernelGGL(lbmnn::bgrad_kernel, dim3(ly.cout), dim3(256), 0, n->stream, dcur, V, n->grads + ly.b_off);
-    NN_HIP(hipGetLastError(), "bias gradient kernel");
     if (l > 0) {
       // gradient with respect to this layer's input = previous output; times the ReLU derivative
       NN_HIP((conv<32, false>(n, dcur, ly.wb, nullptr, 0, n->act[l], dnext, 32)), "conv backward-data");
