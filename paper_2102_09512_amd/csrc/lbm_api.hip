@@ -206,7 +206,7 @@ int lbm_create(lbm_handle* out, int lattice, const int64_t dims[3], double gamma
   const int64_t N = dims[0] * dims[1] * dims[2];
   if (N > ((int64_t)1 << 31) - 1024) return fail(LBM_EINVAL, "lbm_create: more than 2^31 nodes");
 
-  lbm::Tile tile = lbm::default_tile(lattice, opt.precision, dims);
+  lbm::Tile tile = lbm::default_tile(lattice, opt.precision, dims, caloric);
   if (opt.tile[0] || opt.tile[1] || opt.tile[2]) {
     lbm::Tile t{opt.tile[0] ? opt.tile[0] : tile.bx, opt.tile[1] ? opt.tile[1] : tile.by,
                 opt.tile[2] ? opt.tile[2] : tile.chunk};

@@ -125,7 +125,7 @@ hipError_t launch_filter(const Ctx& c, const double* fields, int factor, double*
 hipError_t launch_batch_step(const Batch& b, hipStream_t s, int flip);
 hipError_t launch_toggle(const Batch& b, hipStream_t s);
 // Default launch tile for a lattice/precision and whether a tile is available.
-Tile default_tile(int D, int precision, const int64_t n[3]);
+Tile default_tile(int D, int precision, const int64_t n[3], bool caloric = false);
 bool tile_supported(int D, int precision, const Tile& t, bool caloric = false);
 
 }  // namespace lbm

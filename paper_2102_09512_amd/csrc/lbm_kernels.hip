@@ -700,15 +700,28 @@ static hipError_t launch_step_t(const Ctx& c, const void* src, void* dst) {
 
 // Compiled launch shapes: (D, precision) -> {BX, BY}; the march chunk is a
 // runtime parameter.
-Tile default_tile(int D, int precision, const int64_t n[3]) {
+Tile default_tile(int D, int precision, const int64_t n[3], bool caloric) {
+  (void)precision;
   if (D == 3) {
-    // 64 x 4 tiles, one wavefront per SIMD.  March chunks as long as
-    // possible (fewer prologue planes) while the launch keeps at least one
-    // work-group per compute unit (256).
-    const int64_t tiles = ((n[0] + 63) / 64) * ((n[1] + 3) / 4);
-    int64_t chunk = n[2] * tiles / 256;
-    chunk = chunk < 16 ? 16 : (chunk > 256 ? 256 : chunk);
-    return Tile{64, 4, (int)(chunk < n[2] ? chunk : n[2])};
+    // 64 x 4 tiles, one wavefront per SIMD; 32 x 8 when n_x is a multiple of
+    // 32 but not of 64 (a 64-wide tile would idle half its lanes at the edge),
+    // except for the caloric variant, which is compiled for 64 x 4 only.
+    const bool narrow = !caloric && n[0] % 64 != 0 && n[0] % 32 == 0;
+    const int bx = narrow ? 32 : 64, by = narrow ? 8 : 4;
+    const int64_t tiles = ((n[0] + bx - 1) / bx) * ((n[1] + by - 1) / by);
+    // At least 256 tiles per plane (256^3 and up): one long march chunk per
+    // work-group (fewer prologue planes), about one work-group per CU.
+    // Smaller grids: chunks of at least 4 planes for about two work-groups
+    // per CU (measured at 64^3: 2.1x the throughput of 16-plane chunks).
+    int64_t chunk;
+    if (tiles >= 256) {
+      chunk = n[2] * tiles / 256;
+      chunk = chunk < 16 ? 16 : (chunk > 256 ? 256 : chunk);
+    } else {
+      chunk = n[2] * tiles / 512;
+      chunk = chunk < 4 ? 4 : (chunk > 256 ? 256 : chunk);
+    }
+    return Tile{bx, by, (int)(chunk < n[2] ? chunk : n[2])};
   }
   // D2Q9: rows of 128; chunks short enough for about 1024 work-groups (the
   // whole 2-D field is small), between 4 and 32 rows.
