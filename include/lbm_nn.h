@@ -83,9 +83,13 @@ int lbm_nn_adam_step(lbm_nn net, double lr, double beta1, double beta2, double e
 int lbm_nn_fields_to_planes(int D, int64_t nodes, const double* rho, const double* u, const double* T, float* x,
                             void* hip_stream);
 /* Applies the corrector to a lattice Boltzmann handle whose dims equal the
-   network's: reads rho, u, T (lbm_moments), runs the network and adds the
-   correction y_c out_std_c to field offset + c (the other fields get none)
-   with lbm_fields_add.  Requires c[0] = D + 2. */
+   network's: forms rho, u, T of the stored state, runs the network and adds
+   the correction y_c out_std_c to field offset + c (the other fields get
+   none) by re-equilibration, as lbm_fields_add does, all on the handle's
+   stream and without host synchronisation.  Unlike lbm_fields_add the new
+   fields are not validated: bound the correction with
+   lbm_nn_set_correction_limit (a limit also turns a non-finite output into
+   +-limit) and watch the run with lbm_diagnostics.  Requires c[0] = D + 2. */
 int lbm_nn_correct(lbm_nn net, lbm_handle h);
 
 #ifdef __cplusplus

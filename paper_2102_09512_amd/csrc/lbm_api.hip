@@ -155,6 +155,27 @@ bool fields_valid_host(const double* rho, const double* u, const double* T, int6
 
 }  // namespace
 
+// For the corrector (lbm_nn.hip): the moments of the stored state into
+// c->fields (rho, u_x, u_y, u_z, T, rho E planes) on the handle's stream, and
+// increments applied by re-equilibration without validation or host
+// synchronisation (the caller bounds them).
+int lbm::fields_current(lbm::Ctx* base) {
+  lbm_ctx* c = static_cast<lbm_ctx*>(base);  // every handle is an lbm_ctx
+  if (!c->initialised) return fail(LBM_ESTATE, "corrector: no state (lbm_init_fields)");
+  int rc = ::select_device(c);
+  if (rc) return rc;
+  if ((rc = ::ensure_scratch(c))) return rc;
+  HIP_OR_FAIL(lbm::launch_fields(*c, c->buf[c->cur], c->fields), "moments kernel");
+  return LBM_OK;
+}
+
+int lbm::fields_increment_async(Ctx* c, const double* drho, const double* du, const double* dT) {
+  if (!c->work) HIP_OR_FAIL(hipMalloc(&c->work, sizeof(double) * 10 * (size_t)c->N), "hipMalloc(work)");
+  HIP_OR_FAIL(lbm::launch_fields_plus(*c, c->fields, drho, du, dT, c->work, true), "increment kernel");
+  HIP_OR_FAIL(lbm::launch_fields_add(*c, c->buf[c->cur], c->fields, c->work), "re-equilibration kernel");
+  return LBM_OK;
+}
+
 extern "C" {
 
 void lbm_default_options(lbm_options* opt) {

@@ -122,6 +122,10 @@ hipError_t launch_fields_add(const Ctx& c, void* pops, const double* oldf, const
 hipError_t launch_fields_plus(const Ctx& c, const double* oldf, const double* drho, const double* du, const double* dT,
                               double* newf, bool keep);
 hipError_t launch_filter(const Ctx& c, const double* fields, int factor, double* rho, double* u, double* T);
+// Corrector support (host, lbm_api.hip): moments into c->fields; increments
+// applied by re-equilibration, asynchronously and without validation.
+int fields_current(Ctx* c);
+int fields_increment_async(Ctx* c, const double* drho, const double* du, const double* dT);
 hipError_t launch_batch_step(const Batch& b, hipStream_t s, int flip);
 hipError_t launch_toggle(const Batch& b, hipStream_t s);
 // Default launch tile for a lattice/precision and whether a tile is available.

@@ -769,18 +769,16 @@ int lbm_nn_correct(lbm_nn n, lbm_handle h) {
   int rc = nn_select(n);
   if (rc) return rc;
   const int V = n->V;
-  double* rho = n->dfld;
-  double* u = rho + V;
-  double* T = u + 3 * (size_t)V;
-  double* drho = T + V;
+  double* drho = n->dfld;
   double* du = drho + V;
   double* dT = du + 3 * (size_t)V;
-  // the handle's stream orders moments, network and increments
+  // everything on the handle's stream: moments, network, increments
   hipStream_t saved = n->stream;
   n->stream = h->stream;
-  if ((rc = lbm_moments(h, rho, u, T, LBM_DEVICE)) == LBM_OK) {
-    hipLaunchKernelGGL(lbmnn::fields_to_input_kernel, dim3((V + 255) / 256), dim3(256), 0, n->stream, rho, u, T, D, V,
-                       n->fld);
+  if ((rc = lbm::fields_current(h)) == LBM_OK) {
+    const double* F = h->fields;  // rho, u_x, u_y, u_z, T, rho E planes
+    hipLaunchKernelGGL(lbmnn::fields_to_input_kernel, dim3((V + 255) / 256), dim3(256), 0, n->stream, F, F + V,
+                       F + 4 * (size_t)V, D, V, n->fld);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) rc = nn_hip(e, "fields kernel");
     if (rc == LBM_OK) rc = nn_forward(n, n->fld);
@@ -790,7 +788,7 @@ int lbm_nn_correct(lbm_nn n, lbm_handle h) {
       e = hipGetLastError();
       if (e != hipSuccess) rc = nn_hip(e, "increments kernel");
     }
-    if (rc == LBM_OK) rc = lbm_fields_add(h, drho, du, dT, LBM_DEVICE);
+    if (rc == LBM_OK) rc = lbm::fields_increment_async(h, drho, du, dT);
   }
   n->stream = saved;
   return rc;
