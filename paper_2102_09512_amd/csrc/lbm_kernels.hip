@@ -712,9 +712,12 @@ Tile default_tile(int D, int precision, const int64_t n[3], bool caloric) {
     // March chunks as long as possible (fewer prologue planes) while the
     // launch keeps about one work-group per CU (256): at 256^3 one chunk per
     // tile column; small grids go down to 4-plane chunks (at 64^3 2.1x the
-    // throughput of the 16-plane floor used before).
-    int64_t chunk = n[2] * tiles / 256;
-    chunk = chunk < 4 ? 4 : (chunk > 256 ? 256 : chunk);
+    // throughput of 16-plane chunks).  The length is rounded to the nearest
+    // power of two: at 80^3 and 96^3, 8- and 16-plane chunks ran up to 45%
+    // faster than 6-, 12- or 24-plane ones.
+    const int64_t target = n[2] * tiles / 256;
+    int64_t chunk = 4;
+    while (chunk < 256 && (double)target >= 1.4142135623730951 * (double)chunk) chunk *= 2;
     return Tile{bx, by, (int)(chunk < n[2] ? chunk : n[2])};
   }
   // D2Q9: rows of 128; chunks short enough for about 1024 work-groups (the
