@@ -38,12 +38,6 @@ struct Grid {
 
 __device__ inline int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
-// node v moved by tap t, periodic
-__device__ inline int shifted(int v, int t, const Grid g) {
-  const int x = v % g.nx, y = (v / g.nx) % g.ny, z = v / (g.nx * g.ny);
-  return wrap(x + t % 3 - 1, g.nx) + g.nx * (wrap(y + (t / 3) % 3 - 1, g.ny) + g.ny * wrap(z + t / 9 - 1, g.nz));
-}
-
 // planar FP32 x[c][v] (c < cin) -> bf16 a[v][16], (x - mean) / std, zero padded
 __global__ void __launch_bounds__(256) pack_input_kernel(const float* __restrict__ x, int cin, const float* __restrict__ mean,
                                                          const float* __restrict__ inv_std, __bf16* __restrict__ a, int V) {

@@ -321,3 +321,83 @@ def test_velocity_only_network_loss_gradients_and_correction():
     assert np.abs(after[0] - before[0]).max() < 1e-6
     assert np.abs(after[2] - before[2]).max() < 1e-7
     assert np.abs(after[1] - before[1]).max() > 1e-5
+
+
+def test_fields_set_replaces_the_moments_and_keeps_the_rest():
+    """lbm_fields_set: the moments become the given fields and the state moves
+    by f^eq(new) - f^eq(old) (g likewise), so the non-equilibrium part stays."""
+    lbm = _lbm()
+    dims = (6, 5, 4)
+    rho, u, T = I.smooth_random(3, dims, seed=19, u_amp=0.05)
+    r2, u2, T2 = I.smooth_random(3, dims, seed=20, u_amp=0.05)
+    h = lbm.lbm_create(3, dims, 1.4, 0.7, 0.02)
+    try:
+        lbm.lbm_init_fields(h, rho, u, T)
+        lbm.lbm_step(h, 5)
+        before = np.zeros(lbm.lbm_state_bytes(h) // 8)
+        lbm.lbm_get_state(h, before)
+        m0 = [np.zeros(a.shape) for a in (rho, u, T)]
+        lbm.lbm_moments(h, *m0)
+        lbm.lbm_fields_set(h, r2, u2, T2)
+        after = np.zeros_like(before)
+        lbm.lbm_get_state(h, after)
+        m1 = [np.zeros(a.shape) for a in (rho, u, T)]
+        lbm.lbm_moments(h, *m1)
+        with pytest.raises(lbm.LbmError):  # a non-positive temperature is refused, nothing changes
+            lbm.lbm_fields_set(h, r2, u2, -T2)
+        again = np.zeros_like(before)
+        lbm.lbm_get_state(h, again)
+    finally:
+        lbm.lbm_destroy(h)
+    for a, b in zip(m1, (r2, u2, T2)):
+        assert np.abs(a - b).max() <= 1e-13
+    Q, Nn = 27, rho.size
+    ref = np.zeros((2 * Q, Nn))
+    o0, o1 = m0[1].reshape(3, -1), u2.reshape(3, -1)
+    for k in range(Nn):
+        ro, rn = m0[0].reshape(-1)[k], r2.reshape(-1)[k]
+        to, tn = m0[2].reshape(-1)[k], T2.reshape(-1)[k]
+        ref[:Q, k] = oracle.feq(3, rn, o1[:, k], tn) - oracle.feq(3, ro, o0[:, k], to)
+        ref[Q:, k] = oracle.geq(3, rn, o1[:, k], tn, 2.5) - oracle.geq(3, ro, o0[:, k], to, 2.5)
+    got = (after - before).reshape(2 * Q, Nn)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.array_equal(again, after)
+
+
+def test_fields_to_planes_and_correction_limit():
+    """FP64 fields -> FP32 planes is a plain conversion; with a limit of 0.5
+    no correction exceeds 0.5 out_std, without one the same network moves a
+    field further."""
+    lbm = _lbm()
+    dims = (32, 4, 4)
+    rho, u, T = I.smooth_random(3, dims, seed=21, u_amp=0.05)
+    d = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (rho, u, T)]
+    x = torch.empty((5, rho.size), dtype=torch.float32, device="cuda")
+    lbm.lbm_nn_fields_to_planes(3, *d, x)
+    torch.cuda.synchronize()
+    ref = np.concatenate([rho.reshape(1, -1), u.reshape(3, -1), T.reshape(1, -1)]).astype(np.float32)
+    assert np.array_equal(x.cpu().numpy(), ref)
+    ch = [5, 32, 3]
+    n = lbm.lbm_nn_create(ch, dims)
+    deltas = []
+    try:
+        lbm.lbm_nn_set_params(n, (3.0 * _params(22, channels=ch)).astype(np.float32))  # large outputs
+        lbm.lbm_nn_set_scaling(n, MEAN, STD, OUT[1:4])
+        lbm.lbm_nn_set_output_offset(n, 1)
+        for limit in (0.5, 0.0):
+            lbm.lbm_nn_set_correction_limit(n, limit)
+            h = lbm.lbm_create(3, dims, 1.4, 0.7, 0.02, precision=lbm.LBM_FP32_DEV, T_ref=0.15)
+            try:
+                lbm.lbm_init_fields(h, rho, u, T)
+                lbm.lbm_nn_correct(n, h)
+                m = [np.zeros(a.shape) for a in (rho, u, T)]
+                lbm.lbm_moments(h, *m)
+            finally:
+                lbm.lbm_destroy(h)
+            deltas.append(np.abs(m[1] - u).reshape(3, -1).max(axis=1))
+        with pytest.raises(lbm.LbmError):
+            lbm.lbm_nn_set_correction_limit(n, -1.0)
+    finally:
+        lbm.lbm_nn_destroy(n)
+    assert np.all(deltas[0] <= 0.5 * OUT[1:4] * (1 + 1e-4) + 1e-7)
+    assert np.any(deltas[1] > 0.5 * OUT[1:4] * 1.01)
