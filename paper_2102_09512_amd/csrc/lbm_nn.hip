@@ -530,7 +530,7 @@ int lbm_nn_create(lbm_nn* out, int layers, const int* channels, const int64_t di
   alloc((void**)&n->y, sizeof(float) * (size_t)V * 32);
   alloc((void**)&n->part, sizeof(float) * 28 * (size_t)lbmnn::kGMaxBlocks * 1024);
   alloc((void**)&n->lpart, sizeof(double) * (size_t)((V + 255) / 256));
-  alloc((void**)&n->fld, sizeof(float) * 2 * 16 * (size_t)V);
+  alloc((void**)&n->fld, sizeof(float) * 16 * (size_t)V);
   alloc((void**)&n->dfld, sizeof(double) * 10 * (size_t)V);
   for (Layer& ly : n->layers) {
     alloc((void**)&ly.wp, sizeof(__bf16) * 27 * ly.cinp * 32);
