@@ -538,3 +538,24 @@ def test_batch_refuses_a_general_caloric_law():
     finally:
         for h in hs:
             lbm.lbm_destroy(h)
+
+
+def test_fp32_general_caloric_law_d2q9():
+    """The caloric variant of the D2Q9 kernel with FP32 deviation storage."""
+    D, dims = 2, (64, 48)
+    f = I.smooth_random(D, dims, seed=23, u_amp=0.1, T_amp=0.04)
+    kw = dict(mu=0.02, Pr=0.7, visc_exp=0.76, T_ref=0.15, cv=CV_LAW)
+    out, _, _ = run_gpu(D, dims, f, 100, fp32=True, want_state=False, **kw)
+    s = run_oracle(D, dims, f, 100, **kw)
+    check_fp32_with_floor(D, dims, f, 100, out, s, **kw)
+
+
+def test_fp64_general_caloric_law_zero_gradient():
+    """The caloric law with zero-gradient ends along x and periodic y, z."""
+    D, dims = 3, (20, 12, 8)
+    f = I.smooth_random(D, dims, seed=24, u_amp=0.1, T_amp=0.05)
+    kw = dict(mu=0.02, Pr=0.7, visc_exp=0.76, T_ref=0.15, cv=CV_LAW, bc=(1, 0, 0))
+    out, state, _ = run_gpu(D, dims, f, 100, **kw)
+    s = run_oracle(D, dims, f, 100, **kw)
+    check_fields(out, s, 1e-12)
+    check_pops(state, s, 1e-12)
