@@ -176,6 +176,7 @@ constexpr int kGRow = 40;                           // halo row: 34 nodes, padde
 constexpr int kGPlaneIn = kGHZ * kGHY * kGRow + 8;  // per channel; the 16 extra bytes spread the
 constexpr int kGPlaneD = kGZ * kGY * kGX + 8;       // channel planes over the LDS banks
 constexpr int kGMaxBlocks = 512;
+constexpr int kGSegments = 16;  // first-stage runs of the gradient sum
 
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
@@ -256,6 +257,19 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const __bf16* __restrict__ i
 #pragma unroll
     for (int i = 0; i < 16; ++i) dst[(8 * (i >> 2) + 4 * half + (i & 3)) * 32 + r] = acc[k][i];
   }
+}
+
+// First stage of the gradient sum: part2[t][s][i][o] = sum of part[t][b][i][o]
+// over the s-th of nseg equal runs of b (blockIdx.y = s); fixed order.
+__global__ void __launch_bounds__(256) wgrad_partial_sum_kernel(const float* __restrict__ part, int nblk, int nseg,
+                                                                float* __restrict__ part2) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 28 * 1024) return;
+  const int t = e / 1024, io = e % 1024, sgm = blockIdx.y;
+  const int b0 = (int)((long long)nblk * sgm / nseg), b1 = (int)((long long)nblk * (sgm + 1) / nseg);
+  float acc = 0.f;
+  for (int b = b0; b < b1; ++b) acc += part[((size_t)t * nblk + b) * 1024 + io];
+  part2[((size_t)t * nseg + sgm) * 1024 + io] = acc;
 }
 
 // grad[t][i][o] += sum_b part[t][b][i][o] (t < 27, i < cin, o < cout) and
@@ -410,7 +424,8 @@ struct lbm_nn_ctx {
   std::vector<__bf16*> act;     // act[l]: input of layer l (bf16 [V][16 or 32]); act[L] unused
   __bf16 *dA = nullptr, *dB = nullptr;  // gradient ping-pong, bf16 [V][32]
   float* y = nullptr;                   // network output planes [c_L][V]
-  float* part = nullptr;                // weight-gradient partials
+  float* part = nullptr;                // weight-gradient partials, per work-group
+  float* part2 = nullptr;               // their first-stage sums
   int out_off = 0;                      // output c corrects / is compared with field out_off + c
   double limit = 0.0;                   // lbm_nn_correct clips outputs to [-limit, limit] (0: no clip)
   double* lpart = nullptr;              // loss partials
@@ -529,6 +544,7 @@ int lbm_nn_create(lbm_nn* out, int layers, const int* channels, const int64_t di
   alloc((void**)&n->dB, sizeof(__bf16) * (size_t)V * 32);
   alloc((void**)&n->y, sizeof(float) * (size_t)V * 32);
   alloc((void**)&n->part, sizeof(float) * 28 * (size_t)lbmnn::kGMaxBlocks * 1024);
+  alloc((void**)&n->part2, sizeof(float) * 28 * (size_t)lbmnn::kGSegments * 1024);
   alloc((void**)&n->lpart, sizeof(double) * (size_t)((V + 255) / 256));
   alloc((void**)&n->fld, sizeof(float) * 16 * (size_t)V);
   alloc((void**)&n->dfld, sizeof(double) * 10 * (size_t)V);
@@ -566,7 +582,7 @@ int lbm_nn_destroy(lbm_nn n) {
   (void)nn_select(n);
   if (n->stream) (void)hipStreamSynchronize(n->stream);
   for (void* p : {(void*)n->params, (void*)n->grads, (void*)n->m, (void*)n->v, (void*)n->mean, (void*)n->inv_std,
-                  (void*)n->out_std, (void*)n->inv_out_std, (void*)n->dA, (void*)n->dB, (void*)n->y, (void*)n->part, (void*)n->lpart,
+                  (void*)n->out_std, (void*)n->inv_out_std, (void*)n->dA, (void*)n->dB, (void*)n->y, (void*)n->part, (void*)n->part2, (void*)n->lpart,
                   (void*)n->fld, (void*)n->dfld})
     if (p) (void)hipFree(p);
   for (__bf16* p : n->act)
@@ -703,7 +719,11 @@ int lbm_nn_loss_backward(lbm_nn n, const float* x, const float* target, double* 
       hipLaunchKernelGGL((lbmnn::wgrad_kernel<32>), dim3(nblk), dim3(256), 0, n->stream, n->act[l], dcur, n->part, n->g,
                          ntiles, tpb);
     NN_HIP(hipGetLastError(), "weight gradient kernel");
-    hipLaunchKernelGGL(lbmnn::wgrad_reduce_kernel, dim3(28 * 1024 / 256), dim3(256), 0, n->stream, n->part, nblk,
+    const int nseg = nblk < lbmnn::kGSegments ? nblk : lbmnn::kGSegments;
+    hipLaunchKernelGGL(lbmnn::wgrad_partial_sum_kernel, dim3(28 * 1024 / 256, nseg), dim3(256), 0, n->stream,
+                       n->part, nblk, nseg, n->part2);
+    NN_HIP(hipGetLastError(), "weight gradient partial sums");
+    hipLaunchKernelGGL(lbmnn::wgrad_reduce_kernel, dim3(28 * 1024 / 256), dim3(256), 0, n->stream, n->part2, nseg,
                        ly.cin, ly.cout, n->grads + ly.w_off, n->grads + ly.b_off);
     NN_HIP(hipGetLastError(), "weight gradient reduction");
     if (l > 0) {
