@@ -11,11 +11,14 @@
 // gradient with respect to the layer input, as the convolution with the
 // mirrored taps and exchanged channels, wb[t][o/16][i][o%16].
 //
-// Matrix-core tiles.  One wavefront computes 32 nodes x 32 output channels:
-// lane l supplies A[m = l%32][k = 8(l/32) .. +7] (node m, 8 input channels)
-// and B[k][n = l%32] (8 input channels of output channel n); accumulator i
-// of lane l holds the result for node 8(i/4) + 4(l/32) + i%4 and output
-// channel l%32.
+// Matrix-core tiles (v_mfma_f32_32x32x16_bf16: lane l supplies
+// A[m = l%32][k = 8(l/32) .. +7] and B[k = 8(l/32) .. +7][n = l%32];
+// accumulator i of lane l holds C[m = 8(i/4) + 4(l/32) + i%4][n = l%32]).
+// Convolution: A = weights (m = output channel, k = input channel), B =
+// activations (n = node of a 32-node row), so a lane ends with four
+// consecutive output channels of one node per accumulator group.  Weight
+// gradient: A = input activations (m = input channel, k = node), B = output
+// gradient (n = output channel), summed over nodes.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
