@@ -140,7 +140,7 @@ def run_ensemble(args, torch, lbm, dev):
         lbm.lbm_init_fields(h, *(torch.from_numpy(a).to(dev) for a in b["fields"]))
         hs.append(h)
     batch = lbm.lbm_batch_create(hs)
-    tuned_ms = lbm.lbm_batch_tune(batch, 5)
+    tuned_ms = lbm.lbm_batch_tune(batch, 20)
     tile = lbm.lbm_batch_get_tile(batch)
     _log(f"[bench] {len(hs)} boxes, {N} nodes; tuned tile {tile} ({tuned_ms:.3f} ms per step)")
     lbm.lbm_batch_step(batch, args.warmup, 0)
