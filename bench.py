@@ -274,6 +274,7 @@ def run_learned(args, torch, lbm, dev):
         "plain_equal_time_error": round(summ["plain_equal_time"], 5),
         "equal_time_grids": summ["equal_time_grids"],
         "wins_equal_time": f"{summ['wins_equal_time']}/{summ['seeds']}",
+        "seeds_plain_coarse_unstable": summ["seeds_plain_coarse_unstable"],
         "per_seed": [{"seed": r["seed"], "Ma_t": round(r["Ma_t"], 4),
                       "learned": [round(r["learned"]["error"], 5), round(1e3 * r["learned"]["seconds"], 2)],
                       "plain": [[p["n"], round(p["error"], 5), round(1e3 * p["seconds"], 2)] for p in r["plain"]]}

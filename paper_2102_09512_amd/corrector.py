@@ -420,13 +420,18 @@ def evaluate(w: Workload, net, seeds, Ma_ts, grids=None, log=print):
 
 def summarize(rows):
     """Means over seeds of the three errors, and how many seeds the corrected
-    run beat the equal-time plain run on."""
-    m = lambda key: float(np.mean([r[key]["error"] for r in rows]))
+    run beat the equal-time plain run on.  Seeds on which the plain coarse run
+    itself leaves the stable range (nothing to compare with) are counted
+    apart; a corrected run that fails where the plain one does not counts
+    with an infinite error."""
+    kept = [r for r in rows if math.isfinite(r["plain_coarse"]["error"])]
+    m = lambda key: float(np.mean([r[key]["error"] for r in kept])) if kept else float("nan")
     return {
         "learned": m("learned"),
         "plain_coarse": m("plain_coarse"),
         "plain_equal_time": m("plain_equal_time"),
-        "equal_time_grids": [r["plain_equal_time"]["n"] for r in rows],
-        "wins_equal_time": int(sum(r["learned"]["error"] < r["plain_equal_time"]["error"] for r in rows)),
-        "seeds": len(rows),
+        "equal_time_grids": [r["plain_equal_time"]["n"] for r in kept],
+        "wins_equal_time": int(sum(r["learned"]["error"] < r["plain_equal_time"]["error"] for r in kept)),
+        "seeds": len(kept),
+        "seeds_plain_coarse_unstable": len(rows) - len(kept),
     }
