@@ -75,3 +75,13 @@ def test_seed_tables():
     assert s == list(range(32)) and all(0.3 <= x <= 0.6 for x in m) and len(set(m)) == 32
     e, me = Cr.evaluation_seeds(4)
     assert not set(e) & set(s) and me == pytest.approx([0.3375, 0.4125, 0.4875, 0.5625])
+
+
+def test_summary_sets_apart_seeds_where_the_plain_run_fails():
+    inf = float("inf")
+    row = lambda l, p, q, n=64: {"learned": {"error": l}, "plain_coarse": {"error": p, "n": 64},
+                                "plain_equal_time": {"error": q, "n": n}}
+    s = Cr.summarize([row(0.1, 0.7, 0.6, 80), row(inf, 0.8, 0.8), row(inf, inf, inf)])
+    assert s["seeds"] == 2 and s["seeds_plain_coarse_unstable"] == 1
+    assert s["wins_equal_time"] == 1 and s["learned"] == inf  # a corrected run that fails alone counts
+    assert s["plain_coarse"] == pytest.approx(0.75) and s["equal_time_grids"] == [80, 64]
