@@ -24,7 +24,7 @@ all boxes.
 give teacher-forced training pairs; a 4-layer 3x3x3 convolutional network (32
 channels, bf16 matrix cores, FP32 accumulation) is trained on the GPU for
 --steps epochs; on 4 held-out seeds the corrected 64^3 run, the plain 64^3
-run and plain runs on finer grids are judged by the kinetic-energy spectrum
+run and plain runs on finer grids are compared by the kinetic-energy spectrum
 error against the filtered 256^3 run (RMS of log E over shells 1..32).
 value = the corrected run's error; the plain run given the same wall time is
 reported beside it.
@@ -386,8 +386,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "decomposition is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU decomposition "
+              "is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
