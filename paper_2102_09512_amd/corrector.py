@@ -11,7 +11,7 @@ to two standard deviations of the training corrections: near the method's
 stability limit (early acoustic transients at Ma_t ~ 0.5 on the coarse grid)
 a rare large correction can otherwise tip a run over.
 The corrector is not part of the paper; its training data come from the
-method's own fine runs, and the fine run stays the judge of its error.
+method's own fine runs, and the fine run remains the reference for its error.
 
 Time and viscosity follow the acoustic scaling of the lattice units: one
 coarse step spans n_f / n_c fine steps, and the dynamic viscosity of a grid
@@ -24,7 +24,7 @@ filtered fine fields t form one pair, and then the coarse moments are set to
 t by re-equilibration (lbm_fields_set), which keeps the coarse populations'
 non-equilibrium parts, exactly as a correction does when the network is used.
 
-Judging.  The kinetic-energy spectrum E(k) of the velocity on the coarse grid
+Evaluation.  The kinetic-energy spectrum E(k) of the velocity on the coarse grid
 against that of the filtered fine run, as the RMS over shells 1..n_c/2 of
 log(E / E_ref).  Plain runs on finer grids n_p are timed too; their fields are
 taken to the coarse grid by the same box filter of width L / n_c
