@@ -160,7 +160,7 @@ def test_fp64_central_difference_variant(D):
 
 
 def test_fp64_sod_shock_tube():
-    """Config c1 (reading R10): 800 x 4, x zero-gradient, y periodic."""
+    """Sod shock tube in the lattice scaling of Sec. III.B: 800 x 4, x zero-gradient, y periodic."""
     f = I.sod(800, 4, T_left=0.15)
     kw = dict(mu=0.015, Pr=0.71, bc=(1, 0, 0))
     for steps, tol in ((100, 1e-12), (1000, 1e-10)):
@@ -392,7 +392,7 @@ def test_tile_shapes_give_the_same_result():
 
 
 def test_fp32_turbulence_statistics_2000_steps_within_one_percent():
-    """Config c3 (256^3 D3Q27, Ma_t 0.5, Re_lambda 72): FP32 deviation storage
+    """Decaying turbulence (256^3 D3Q27, Ma_t 0.5, Re_lambda 72): FP32 deviation storage
     against FP64 storage (the latter parity-checked against the oracle) over
     2000 steps (about 10 large-eddy turnovers): K, Ma_t, theta_rms, rho_rms
     and enstrophy every 250 steps within 1%."""
