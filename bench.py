@@ -66,9 +66,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, precision: str):
+def measured_traffic(workload: str, precision: str, tile):
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source."""
+    taken on the current kernel source with the same launch tile."""
     path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
     try:
         with open(path) as fh:
@@ -76,7 +76,8 @@ def measured_traffic(workload: str, precision: str):
     except (OSError, ValueError):
         return None
     for r in rec.get("records", []):
-        if r.get("workload") == workload and r.get("precision") == precision and r.get("source") == kernel_source_hash():
+        if (r.get("workload") == workload and r.get("precision") == precision and list(r.get("tile", [])) == list(tile)
+                and r.get("source") == kernel_source_hash()):
             return r.get("bytes_per_launch")
     return None
 
@@ -422,8 +423,9 @@ def main():
                        tile=tile, deriv_scheme=lbm.LBM_DERIV_CENTRAL if args.deriv == "central" else lbm.LBM_DERIV_UPWIND)
     lbm.lbm_set_stream(h, stream)
     lbm.lbm_init_fields(h, *(torch.from_numpy(a).to(dev) for a in w["fields"]))
+    used_tile = lbm.lbm_get_tile(h)
 
-    _log(f"[bench] warmup {args.warmup} steps")
+    _log(f"[bench] launch tile {used_tile}{'' if tile else ' (default)'}; warmup {args.warmup} steps")
     lbm.lbm_step(h, args.warmup)
     torch.cuda.synchronize()
 
@@ -472,7 +474,7 @@ def main():
     mlups = N * args.steps / wall / 1e6
     achieved = bytes_per_node * N / avg_kernel_s / 1e9
     workload = w["label"].format(prec=args.precision) + (" central-anomaly" if args.deriv == "central" else "")
-    traffic = measured_traffic(workload, args.precision)
+    traffic = measured_traffic(workload, args.precision, used_tile)
     lattice = f"D{D}Q{Q}"
     out = {
         "metric": f"MLUPS ({lattice} fused stream+collide)",
@@ -489,7 +491,8 @@ def main():
         "data": "synthetic (seeded, no dataset)",
         "config": {"workload": workload, "lattice": lattice, "nodes": N, "dims": list(dims[:D]),
                    "bytes_per_node_update": bytes_per_node, "diag_every": args.diag_every,
-                   "tile": list(tile) if tile else "default", "parallelism": "single GPU"},
+                   "tile": list(used_tile), "tile_source": "given" if tile else "default",
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "kernel": "step_kernel", "avg_kernel_ms": round(avg_kernel_s * 1e3, 4),

@@ -76,7 +76,8 @@ typedef struct {
   double T_ref;         /* T_0 of the power law and reference temperature of FP32 deviations; default 1/3 */
   double rho_ref;       /* reference density of FP32 deviations; default 1 */
   int deriv_scheme;     /* LBM_DERIV_UPWIND (default) or LBM_DERIV_CENTRAL */
-  int tile[3];          /* launch shape of the step kernel: x width, y width (D3Q27), march chunk; 0 = default */
+  int tile[3];          /* launch shape of the step kernel: x width, y width (D3Q27), march chunk; 0 = default
+                           (a zero chunk with a given shape: the default chunk for that shape) */
   double u_ref[3];      /* reference velocity of FP32 deviations (|u_ref_a| < 1); default 0 */
   double cv_poly[3];    /* caloric law (Sec. II.A, Eq. (6)): C_v(T) = cv_poly[0] + cv_poly[1] T + cv_poly[2] T^2,
                            U(T) = its integral from 0, T recovered from U by Newton's method; needs
@@ -142,6 +143,9 @@ int lbm_get_state(lbm_handle h, void* buf, size_t bytes, int mem);
    dims and precision; the step counter is set to step. */
 int lbm_set_state(lbm_handle h, const void* buf, size_t bytes, int mem, int64_t step);
 int64_t lbm_step_count(lbm_handle h);
+/* Launch tile {bx, by, chunk} of the handle's step kernel (the default chosen
+   at lbm_create, or lbm_options.tile).  LBM_EINVAL on a NULL argument. */
+int lbm_get_tile(lbm_handle h, int tile[3]);
 /* Message of the last failure on this thread ("" if none).  h is unused. */
 const char* lbm_last_error(lbm_handle h);
 /* Adds increments to the macroscopic fields of the stored state: with (rho,
@@ -187,7 +191,8 @@ int lbm_batch_destroy(lbm_batch b);
 int lbm_batch_set_stream(lbm_batch b, void* hip_stream);
 /* Shared launch tile {bx, by, chunk}: bx, by one of the compiled shapes of the
    lattice (as in lbm_options.tile); chunk > 0 for every box, 0 for each box's
-   default.  LBM_EINVAL if not available.  Drops a captured graph. */
+   default chunk with that shape.  LBM_EINVAL if not available.  Drops a
+   captured graph. */
 int lbm_batch_set_tile(lbm_batch b, const int tile[3]);
 int lbm_batch_get_tile(lbm_batch b, int tile[3]);
 /* Autotuner: times every compiled shape with several march-chunk lengths over

@@ -229,9 +229,9 @@ int lbm_create(lbm_handle* out, int lattice, const int64_t dims[3], double gamma
 
   lbm::Tile tile = lbm::default_tile(lattice, opt.precision, dims, caloric);
   if (opt.tile[0] || opt.tile[1] || opt.tile[2]) {
-    lbm::Tile t{opt.tile[0] ? opt.tile[0] : tile.bx, opt.tile[1] ? opt.tile[1] : tile.by,
-                opt.tile[2] ? opt.tile[2] : tile.chunk};
+    lbm::Tile t{opt.tile[0] ? opt.tile[0] : tile.bx, opt.tile[1] ? opt.tile[1] : tile.by, opt.tile[2]};
     if (lattice == LBM_D2Q9 && !opt.tile[1]) t.by = 1;
+    if (!t.chunk && t.bx > 0 && t.by > 0) t.chunk = lbm::default_chunk(lattice, dims, t.bx, t.by);
     if (!lbm::tile_supported(lattice, opt.precision, t, caloric) || t.chunk < 1)
       return fail(LBM_EINVAL, caloric ? "lbm_create: with cv_poly only the default launch shape is compiled"
                                       : "lbm_create: launch tile not available");
@@ -282,13 +282,14 @@ int lbm_destroy(lbm_handle h) {
   if (!h) return LBM_OK;
   Ctx* c = h;
   select_device(c);
-  if (c->stream) hipStreamSynchronize(c->stream);
+  // Teardown is best effort: errors here have nowhere to go.
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (int k = 0; k < 2; ++k)
-    if (c->buf[k]) hipFree(c->buf[k]);
-  if (c->fields) hipFree(c->fields);
-  if (c->work) hipFree(c->work);
-  if (c->partial) hipFree(c->partial);
-  if (c->diag_dev) hipFree(c->diag_dev);
+    if (c->buf[k]) (void)hipFree(c->buf[k]);
+  if (c->fields) (void)hipFree(c->fields);
+  if (c->work) (void)hipFree(c->work);
+  if (c->partial) (void)hipFree(c->partial);
+  if (c->diag_dev) (void)hipFree(c->diag_dev);
   delete c;
   return LBM_OK;
 }
@@ -404,6 +405,14 @@ int lbm_diagnostics(lbm_handle h, lbm_diag* out) {
   out->nonpositive = (int64_t)v[19];
   out->nodes = (int64_t)v[20];
   c->unstable = out->nonfinite > 0 || out->nonpositive > 0;
+  return LBM_OK;
+}
+
+int lbm_get_tile(lbm_handle h, int tile[3]) {
+  if (!h || !tile) return fail(LBM_EINVAL, "lbm_get_tile: NULL argument");
+  tile[0] = h->tile.bx;
+  tile[1] = h->tile.by;
+  tile[2] = h->tile.chunk;
   return LBM_OK;
 }
 
@@ -553,7 +562,7 @@ int batch_layout(Batch* b) {
     const lbm::Ctx* c = b->boxes[i];
     lbm::Tile t = b->tile;
     const int64_t nm = c->lattice == 3 ? c->n[2] : c->n[1];
-    if (t.chunk <= 0) t.chunk = lbm::default_tile(c->lattice, c->precision, c->n).chunk;
+    if (t.chunk <= 0) t.chunk = lbm::default_chunk(c->lattice, c->n, t.bx, t.by);
     if (t.chunk > nm) t.chunk = (int)nm;
     lbm::BoxEntry& e = b->host[i];
     fill_step_params(c, t, e.p);
@@ -616,9 +625,10 @@ int batch_capture(Batch* b, int graph_steps) {
 std::vector<lbm::Tile> batch_candidates(int D) {
   std::vector<lbm::Tile> v;
   if (D == 3) {
-    for (int chunk : {16, 32, 64, 128, 256}) {
+    for (int chunk : {4, 8, 16, 32, 64, 128, 256}) {
       v.push_back({64, 4, chunk});
       v.push_back({32, 8, chunk});
+      v.push_back({64, 8, chunk});
     }
   } else {
     for (int bx : {64, 128, 256})

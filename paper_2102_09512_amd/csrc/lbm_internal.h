@@ -128,8 +128,10 @@ int fields_current(Ctx* c);
 int fields_increment_async(Ctx* c, const double* drho, const double* du, const double* dT);
 hipError_t launch_batch_step(const Batch& b, hipStream_t s, int flip);
 hipError_t launch_toggle(const Batch& b, hipStream_t s);
-// Default launch tile for a lattice/precision and whether a tile is available.
+// Default launch tile for a lattice/precision, the default march chunk for a
+// given shape, and whether a tile is available.
 Tile default_tile(int D, int precision, const int64_t n[3], bool caloric = false);
+int default_chunk(int D, const int64_t n[3], int bx, int by);
 bool tile_supported(int D, int precision, const Tile& t, bool caloric = false);
 
 }  // namespace lbm

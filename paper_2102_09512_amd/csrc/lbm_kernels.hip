@@ -698,34 +698,77 @@ static hipError_t launch_step_t(const Ctx& c, const void* src, void* dst) {
   return hipGetLastError();
 }
 
-// Compiled launch shapes: (D, precision) -> {BX, BY}; the march chunk is a
-// runtime parameter.
-Tile default_tile(int D, int precision, const int64_t n[3], bool caloric) {
-  (void)precision;
-  if (D == 3) {
-    // 64 x 4 tiles, one wavefront per SIMD; 32 x 8 when n_x is a multiple of
-    // 32 but not of 64 (a 64-wide tile would idle half its lanes at the edge),
-    // except for the caloric variant, which is compiled for 64 x 4 only.
-    const bool narrow = !caloric && n[0] % 64 != 0 && n[0] % 32 == 0;
-    const int bx = narrow ? 32 : 64, by = narrow ? 8 : 4;
-    const int64_t tiles = ((n[0] + bx - 1) / bx) * ((n[1] + by - 1) / by);
-    // March chunks as long as possible (fewer prologue planes) while the
-    // launch keeps about one work-group per CU (256): at 256^3 one chunk per
-    // tile column; small grids go down to 4-plane chunks (at 64^3 2.1x the
-    // throughput of 16-plane chunks).  The length is rounded to the nearest
-    // power of two: at 80^3 and 96^3, 8- and 16-plane chunks ran up to 45%
-    // faster than 6-, 12- or 24-plane ones.
-    const int64_t target = n[2] * tiles / 256;
-    int64_t chunk = 4;
-    while (chunk < 256 && (double)target >= 1.4142135623730951 * (double)chunk) chunk *= 2;
-    return Tile{bx, by, (int)(chunk < n[2] ? chunk : n[2])};
+// Estimated time of a 3-D launch, in units of one 64 x 4 tile plane.  A
+// work-group marches `chunk` planes of one tile column and occupies a whole
+// CU (one wavefront per SIMD for the 256-thread shapes, two for 64 x 8), so
+// the launch runs in rounds of 256 work-groups.  Each chunk pays a prologue
+// (the planes next to it are loaded and their moments computed before its
+// first collision) worth about 8 planes in the measured chunk sweeps.  w is
+// the time of one tile plane of the shape relative to 64 x 4: 32 x 8 moves
+// the same nodes a little slower (1.02), 64 x 8 moves twice the nodes with
+// two wavefronts per SIMD hiding more latency (1.8).
+static double march_cost(const int64_t n[3], int bx, int by, int64_t chunk, double w) {
+  const int64_t tiles = ((n[0] + bx - 1) / bx) * ((n[1] + by - 1) / by);
+  const int64_t blocks = tiles * ((n[2] + chunk - 1) / chunk);
+  return (double)((blocks + 255) / 256) * (double)(chunk + 8) * w;
+}
+
+// The power-of-two chunk of 4 to 256 planes, or the whole march axis, with
+// the lowest march_cost for one 3-D launch shape.  Chunks stay powers of
+// two: at 80^3 and 96^3, 8- and 16-plane chunks ran up to 45% faster than
+// 6-, 12- or 24-plane ones.
+static int64_t best_chunk3(const int64_t n[3], int bx, int by, double w, double* cost) {
+  int64_t best = 1;
+  double best_cost = -1.0;
+  for (int64_t chunk = 4;; chunk *= 2) {
+    const int64_t c = chunk < n[2] ? chunk : n[2];
+    const double k = march_cost(n, bx, by, c, w);
+    if (best_cost < 0.0 || k < best_cost) {
+      best_cost = k;
+      best = c;
+    }
+    if (chunk >= n[2] || chunk >= 256) break;
   }
-  // D2Q9: rows of 128; chunks short enough for about 1024 work-groups (the
-  // whole 2-D field is small), between 4 and 32 rows.
-  const int64_t tiles = (n[0] + 127) / 128;
+  if (cost) *cost = best_cost;
+  return best;
+}
+
+int default_chunk(int D, const int64_t n[3], int bx, int by) {
+  if (D == 3) return (int)best_chunk3(n, bx, by, 1.0, nullptr);
+  // D2Q9: chunks short enough for about 1024 work-groups (the whole 2-D
+  // field is small), between 4 and 32 rows.
+  const int64_t tiles = (n[0] + bx - 1) / bx;
   int64_t chunk = n[1] * tiles / 1024;
   chunk = chunk < 4 ? 4 : (chunk > 32 ? 32 : chunk);
-  return Tile{128, 1, (int)(chunk < n[1] ? chunk : n[1])};
+  return (int)(chunk < n[1] ? chunk : n[1]);
+}
+
+// Default launch shape and march chunk.  D3Q27: the compiled shape with the
+// lowest march_cost at its best chunk — 64 x 4, 32 x 8 and, for FP32
+// storage, 64 x 8 (the only 512-thread shape that fits 256 registers
+// without spilling); the caloric variant is compiled for 64 x 4 only.  On
+// one MI355X this picks 64 x 4 with 4-plane chunks at 64^3 (2.1x the
+// throughput of 16-plane chunks), 32 x 8 / 16 at 96^3, 64 x 4 / 32 at
+// 128^3, 64 x 8 / 64 at 192^3 and 64 x 8 / 128 at 256^3 (5% faster than
+// 64 x 4 / 256 there).  D2Q9: rows of 128.
+Tile default_tile(int D, int precision, const int64_t n[3], bool caloric) {
+  if (D == 3) {
+    struct Shape { int bx, by; double w; };
+    const Shape shapes[3] = {{64, 4, 1.0}, {32, 8, 1.02}, {64, 8, 1.8}};
+    const int nshapes = caloric ? 1 : (precision == LBM_FP32_DEV ? 3 : 2);
+    Tile best{64, 4, 1};
+    double best_cost = -1.0;
+    for (int s = 0; s < nshapes; ++s) {
+      double k = 0.0;
+      const int64_t c = best_chunk3(n, shapes[s].bx, shapes[s].by, shapes[s].w, &k);
+      if (best_cost < 0.0 || k < best_cost) {
+        best_cost = k;
+        best = Tile{shapes[s].bx, shapes[s].by, (int)c};
+      }
+    }
+    return best;
+  }
+  return Tile{128, 1, default_chunk(D, n, 128, 1)};
 }
 
 bool tile_supported(int D, int precision, const Tile& t, bool caloric) {

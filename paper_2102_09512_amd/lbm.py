@@ -106,12 +106,13 @@ def _load():
     L.lbm_batch_set_stream.argtypes = [vp, vp]
     L.lbm_batch_set_tile.argtypes = [vp, C.POINTER(C.c_int)]
     L.lbm_batch_get_tile.argtypes = [vp, C.POINTER(C.c_int)]
+    L.lbm_get_tile.argtypes = [vp, C.POINTER(C.c_int)]
     L.lbm_batch_tune.argtypes = [vp, C.c_int, dp]
     L.lbm_batch_step.argtypes = [vp, i64, C.c_int]
     for name in ("lbm_create", "lbm_destroy", "lbm_set_stream", "lbm_init_fields", "lbm_step", "lbm_moments",
                  "lbm_diagnostics", "lbm_get_state", "lbm_set_state", "lbm_device_copy", "lbm_batch_create",
                  "lbm_batch_destroy", "lbm_batch_set_stream", "lbm_batch_set_tile", "lbm_batch_get_tile",
-                 "lbm_batch_tune", "lbm_batch_step", "lbm_fields_add", "lbm_filter_moments", "lbm_nn_create",
+                 "lbm_get_tile", "lbm_batch_tune", "lbm_batch_step", "lbm_fields_add", "lbm_filter_moments", "lbm_nn_create",
                  "lbm_nn_destroy", "lbm_nn_set_stream", "lbm_nn_set_params", "lbm_nn_get_params", "lbm_nn_get_grads",
                  "lbm_nn_zero_grad", "lbm_nn_set_scaling", "lbm_nn_forward", "lbm_nn_loss_backward",
                  "lbm_nn_adam_step", "lbm_nn_correct", "lbm_nn_fields_to_planes", "lbm_fields_set",
@@ -246,6 +247,12 @@ def lbm_diagnostics(h) -> dict:
         v = getattr(d, name)
         out[name] = list(v) if isinstance(v, C.Array) else v
     return out
+
+
+def lbm_get_tile(h):
+    t = (C.c_int * 3)()
+    _check(_L.lbm_get_tile(h, t))
+    return tuple(t)
 
 
 def lbm_state_bytes(h) -> int:

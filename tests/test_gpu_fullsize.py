@@ -127,7 +127,7 @@ def test_shock_vortex_1024_full_field_fp32():
 
 def _sample_nodes(n, seed=3, count=3000):
     edges_x = [0, 1, 62, 63, 64, 65, 127, 128, 191, 192, 254, 255]
-    edges_y = [0, 1, 2, 3, 4, 5, 127, 128, 251, 252, 254, 255]
+    edges_y = [0, 1, 2, 3, 4, 5, 7, 8, 9, 127, 128, 247, 248, 251, 252, 254, 255]  # 4- and 8-row tile edges
     edges_z = [0, 1, 2, 127, 128, 253, 254, 255]
     zz, yy, xx = np.meshgrid(edges_z, edges_y, edges_x, indexing="ij")
     structured = (xx + n * (yy + n * zz)).ravel()
