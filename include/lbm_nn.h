@@ -71,8 +71,14 @@ int lbm_nn_forward(lbm_nn net, const float* x, float* y);
    f = offset + c, y = network(normalised x), t the target fields (c[0]
    planes, device); the corrected field x_f + y_c out_std_c is compared with
    t_f in units of out_std_c.
-   *loss (host, may be NULL) receives L.  Synchronous. */
+   *loss (host) receives L, and the call is synchronous.  loss NULL: nothing
+   waits for the GPU; L is added to a device-side running sum instead (see
+   lbm_nn_take_loss). */
 int lbm_nn_loss_backward(lbm_nn net, const float* x, const float* target, double* loss);
+/* The running sum of the losses of the lbm_nn_loss_backward calls made with
+   loss NULL since the last call of this function (*sum, host) and their
+   number (*count, host, may be NULL); resets both.  Synchronous. */
+int lbm_nn_take_loss(lbm_nn net, double* sum, int64_t* count);
 /* One Adam step on the accumulated gradients (scaled by grad_scale), step
    count t >= 1 for the bias correction; then the bf16 weight copies are
    rebuilt. */

@@ -282,17 +282,19 @@ def train(w: Workload, pairs, epochs=20, lr=1e-3, batch=4, seed=0, log=print) ->
         hist = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        lbm.lbm_nn_take_loss(net)  # start the device-side loss sum from zero
         for ep in range(epochs):
             perm = rng.permutation(P)
-            s = 0.0
             for b in range(0, P, batch):
                 mb = perm[b: b + batch]
                 lbm.lbm_nn_zero_grad(net)
-                for i in mb:
-                    s += lbm.lbm_nn_loss_backward(net, pairs[i, 0], pairs[i, 1])
+                for i in mb:  # asynchronous: the host does not wait for the GPU within an epoch
+                    lbm.lbm_nn_loss_backward(net, pairs[i, 0], pairs[i, 1], sync=False)
                 step += 1
                 rate = lr * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * (step - 1) / max(total - 1, 1))))
                 lbm.lbm_nn_adam_step(net, rate, 0.9, 0.999, 1e-8, 1.0 / len(mb), step)
+            s, count = lbm.lbm_nn_take_loss(net)
+            assert count == P
             hist.append(s / P)
             log(f"[train] epoch {ep + 1}/{epochs}: loss {hist[-1]:.4f} ({time.perf_counter() - t0:.1f} s)")
         torch.cuda.synchronize()

@@ -343,6 +343,22 @@ __global__ void __launch_bounds__(256) loss_kernel(const float* __restrict__ y, 
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// acc[0] += scale * (sum of partial[0 .. n-1]) in a fixed order (one
+// work-group): the loss of one sample added to a device-side running sum.
+__global__ void __launch_bounds__(256) loss_accumulate_kernel(const double* __restrict__ partial, int n, double scale,
+                                                              double* __restrict__ acc) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += partial[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) acc[0] += scale * red[0];
+}
+
 __global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ p, const float* __restrict__ g,
                                                    float* __restrict__ m, float* __restrict__ v, long long n, float lr,
                                                    float b1, float b2, float eps, float gscale, float c1, float c2) {
@@ -454,6 +470,8 @@ struct lbm_nn_ctx {
   int out_off = 0;                      // output c corrects / is compared with field out_off + c
   double limit = 0.0;                   // lbm_nn_correct clips outputs to [-limit, limit] (0: no clip)
   double* lpart = nullptr;              // loss partials
+  double* loss_acc = nullptr;           // running sum of asynchronous losses (device, 1 value)
+  long long loss_count = 0;             // losses added to it since the last lbm_nn_take_loss
   float* fld = nullptr;                 // corrector staging: fields and correction (FP32)
   double* dfld = nullptr;               // FP64 fields / increments for lbm
 };
@@ -571,6 +589,7 @@ int lbm_nn_create(lbm_nn* out, int layers, const int* channels, const int64_t di
   alloc((void**)&n->part, sizeof(float) * 28 * (size_t)lbmnn::kGMaxBlocks * 1024);
   alloc((void**)&n->part2, sizeof(float) * 28 * (size_t)lbmnn::kGSegments * 1024);
   alloc((void**)&n->lpart, sizeof(double) * (size_t)((V + 255) / 256));
+  alloc((void**)&n->loss_acc, sizeof(double));
   alloc((void**)&n->fld, sizeof(float) * 16 * (size_t)V);
   alloc((void**)&n->dfld, sizeof(double) * 10 * (size_t)V);
   for (Layer& ly : n->layers) {
@@ -583,6 +602,7 @@ int lbm_nn_create(lbm_nn* out, int layers, const int* channels, const int64_t di
     if (e == hipSuccess) e = hipMemset(n->grads, 0, P);
     if (e == hipSuccess) e = hipMemset(n->m, 0, P);
     if (e == hipSuccess) e = hipMemset(n->v, 0, P);
+    if (e == hipSuccess) e = hipMemset(n->loss_acc, 0, sizeof(double));
     if (e == hipSuccess) e = hipMemcpy(n->mean, mean.data(), 16 * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(n->inv_std, one.data(), 16 * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(n->out_std, one.data(), 32 * sizeof(float), hipMemcpyHostToDevice);
@@ -608,7 +628,7 @@ int lbm_nn_destroy(lbm_nn n) {
   if (n->stream) (void)hipStreamSynchronize(n->stream);
   for (void* p : {(void*)n->params, (void*)n->grads, (void*)n->m, (void*)n->v, (void*)n->mean, (void*)n->inv_std,
                   (void*)n->out_std, (void*)n->inv_out_std, (void*)n->dA, (void*)n->dB, (void*)n->y, (void*)n->part, (void*)n->part2, (void*)n->lpart,
-                  (void*)n->fld, (void*)n->dfld})
+                  (void*)n->loss_acc, (void*)n->fld, (void*)n->dfld})
     if (p) (void)hipFree(p);
   for (__bf16* p : n->act)
     if (p) (void)hipFree(p);
@@ -767,7 +787,24 @@ int lbm_nn_loss_backward(lbm_nn n, const float* x, const float* target, double* 
     double s = 0.0;
     for (double x2 : h) s += x2;
     *loss = s / ((double)C * V);
+  } else {
+    hipLaunchKernelGGL(lbmnn::loss_accumulate_kernel, dim3(1), dim3(256), 0, n->stream, n->lpart, lblocks,
+                       1.0 / ((double)C * V), n->loss_acc);
+    NN_HIP(hipGetLastError(), "loss accumulation");
+    ++n->loss_count;
   }
+  return LBM_OK;
+}
+
+int lbm_nn_take_loss(lbm_nn n, double* sum, int64_t* count) {
+  if (!n || !sum) return nn_fail(LBM_EINVAL, "lbm_nn_take_loss: NULL argument");
+  int rc = nn_select(n);
+  if (rc) return rc;
+  NN_HIP(hipMemcpyAsync(sum, n->loss_acc, sizeof(double), hipMemcpyDeviceToHost, n->stream), "copy loss sum");
+  NN_HIP(hipMemsetAsync(n->loss_acc, 0, sizeof(double), n->stream), "reset loss sum");
+  NN_HIP(hipStreamSynchronize(n->stream), "hipStreamSynchronize");
+  if (count) *count = n->loss_count;
+  n->loss_count = 0;
   return LBM_OK;
 }
 

@@ -95,6 +95,7 @@ def _load():
     L.lbm_nn_set_scaling.argtypes = [vp, dp, dp, dp]
     L.lbm_nn_forward.argtypes = [vp, vp, vp]
     L.lbm_nn_loss_backward.argtypes = [vp, vp, vp, dp]
+    L.lbm_nn_take_loss.argtypes = [vp, dp, C.POINTER(i64)]
     L.lbm_nn_adam_step.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, i64]
     L.lbm_nn_correct.argtypes = [vp, vp]
     L.lbm_nn_set_output_offset.argtypes = [vp, C.c_int]
@@ -115,7 +116,7 @@ def _load():
                  "lbm_get_tile", "lbm_batch_tune", "lbm_batch_step", "lbm_fields_add", "lbm_filter_moments", "lbm_nn_create",
                  "lbm_nn_destroy", "lbm_nn_set_stream", "lbm_nn_set_params", "lbm_nn_get_params", "lbm_nn_get_grads",
                  "lbm_nn_zero_grad", "lbm_nn_set_scaling", "lbm_nn_forward", "lbm_nn_loss_backward",
-                 "lbm_nn_adam_step", "lbm_nn_correct", "lbm_nn_fields_to_planes", "lbm_fields_set",
+                 "lbm_nn_adam_step", "lbm_nn_take_loss", "lbm_nn_correct", "lbm_nn_fields_to_planes", "lbm_fields_set",
                  "lbm_nn_set_output_offset", "lbm_nn_set_correction_limit"):
         getattr(L, name).restype = C.c_int
     return L
@@ -435,14 +436,26 @@ def lbm_nn_forward(n, x, y) -> int:
     return _check(_L.lbm_nn_forward(n, px, py))
 
 
-def lbm_nn_loss_backward(n, x, target) -> float:
+def lbm_nn_loss_backward(n, x, target, sync: bool = True):
+    """The sample's loss (synchronous), or None with sync False: the loss is
+    then added to the device-side sum that lbm_nn_take_loss returns."""
     px, kx, _a = _arg(x, dtype=np.float32)
     pt, kt, _b = _arg(target, dtype=np.float32)
     if kx != LBM_DEVICE or kt != LBM_DEVICE:
         raise ValueError("lbm_nn_loss_backward takes device tensors")
+    if not sync:
+        _check(_L.lbm_nn_loss_backward(n, px, pt, None))
+        return None
     loss = C.c_double()
     _check(_L.lbm_nn_loss_backward(n, px, pt, C.byref(loss)))
     return loss.value
+
+
+def lbm_nn_take_loss(n):
+    """(sum, count) of the asynchronous losses since the last call; resets them."""
+    total, count = C.c_double(), C.c_int64()
+    _check(_L.lbm_nn_take_loss(n, C.byref(total), C.byref(count)))
+    return total.value, int(count.value)
 
 
 def lbm_nn_adam_step(n, lr, beta1=0.9, beta2=0.999, eps=1e-8, grad_scale=1.0, t=1) -> int:

@@ -170,6 +170,17 @@ def test_training_reduces_the_loss():
             lbm.lbm_nn_adam_step(n, 2e-3, 0.9, 0.999, 1e-8, 1.0 / len(xs), it)
         print(f"  loss {losses[0]:.3e} -> {losses[-1]:.3e}", flush=True)
         assert losses[-1] < 0.1 * losses[0]
+        # asynchronous losses: the device-side sum equals the synchronous ones
+        lbm.lbm_nn_zero_grad(n)
+        sync = [lbm.lbm_nn_loss_backward(n, x, t) for x, t in zip(xs, ts)]
+        g_sync = lbm.lbm_nn_get_grads(n)
+        lbm.lbm_nn_zero_grad(n)
+        assert all(lbm.lbm_nn_loss_backward(n, x, t, sync=False) is None for x, t in zip(xs, ts))
+        total, count = lbm.lbm_nn_take_loss(n)
+        assert count == len(xs)
+        assert total == pytest.approx(sum(sync), rel=1e-13)
+        assert np.array_equal(lbm.lbm_nn_get_grads(n), g_sync)  # same gradients either way
+        assert lbm.lbm_nn_take_loss(n) == (0.0, 0)
     finally:
         lbm.lbm_nn_destroy(n)
 
