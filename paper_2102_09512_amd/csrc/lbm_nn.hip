@@ -322,7 +322,8 @@ __global__ void __launch_bounds__(256) loss_kernel(const float* __restrict__ y, 
   double s = 0.0;
   if (v < V) {
     const float scale = 2.f / ((float)C * (float)V);
-#pragma unroll 1
+    bf8 o[4];  // the node's 32 gradient channels, stored as four 16-byte words
+#pragma unroll
     for (int c = 0; c < 32; ++c) {
       float g = 0.f;
       if (c < C) {
@@ -331,8 +332,10 @@ __global__ void __launch_bounds__(256) loss_kernel(const float* __restrict__ y, 
         s += (double)rr * rr;
         g = scale * rr;
       }
-      dout[(size_t)v * 32 + c] = (__bf16)g;
+      o[c / 8][c % 8] = (__bf16)g;
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) *(bf8*)(dout + (size_t)v * 32 + 8 * q) = o[q];
   }
   red[threadIdx.x] = s;
   __syncthreads();
