@@ -157,6 +157,8 @@ def test_turbulence_256_sampled_step(fp32):
     h = lbm.lbm_create(3, (n, n, n), 1.4, 0.7, mu, precision=lbm.LBM_FP32_DEV if fp32 else lbm.LBM_FP64,
                        visc_exponent=0.76, T_ref=0.15, rho_ref=1.0)
     try:
+        # the benchmark's launch shape: 64 x 8 tiles in 128-plane chunks (FP32), 64 x 4 in one chunk (FP64)
+        assert lbm.lbm_get_tile(h) == ((64, 8, 128) if fp32 else (64, 4, 256))
         lbm.lbm_set_stream(h, torch.cuda.current_stream())
         lbm.lbm_init_fields(h, *(torch.from_numpy(a).cuda() for a in fields))
         lbm.lbm_step(h, warm)

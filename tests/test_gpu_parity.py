@@ -391,6 +391,23 @@ def test_tile_shapes_give_the_same_result():
             assert np.abs(state - ref).max() <= 1e-13 * np.abs(ref).max(), tile  # rounding only
 
 
+def test_tile_query_and_default_chunk_for_a_given_shape():
+    """lbm_get_tile reports the launch tile; a zero chunk with a given shape
+    takes the default chunk for that shape (70 x 20 x 13 with 64 x 8 tiles:
+    six tile columns, so the shortest chunk, 4 planes)."""
+    lbm = _lbm()
+    h = lbm.lbm_create(3, (70, 20, 13), 1.4, 0.7, 0.02, tile=(64, 8, 0))
+    try:
+        assert lbm.lbm_get_tile(h) == (64, 8, 4)
+    finally:
+        lbm.lbm_destroy(h)
+    h = lbm.lbm_create(3, (70, 20, 13), 1.4, 0.7, 0.02, tile=(32, 8, 9))
+    try:
+        assert lbm.lbm_get_tile(h) == (32, 8, 9)
+    finally:
+        lbm.lbm_destroy(h)
+
+
 def test_fp32_turbulence_statistics_2000_steps_within_one_percent():
     """Decaying turbulence (256^3 D3Q27, Ma_t 0.5, Re_lambda 72): FP32 deviation storage
     against FP64 storage (the latter parity-checked against the oracle) over
