@@ -632,7 +632,7 @@ std::vector<lbm::Tile> batch_candidates(int D) {
     }
   } else {
     for (int bx : {64, 128, 256})
-      for (int chunk : {4, 8, 16, 32}) v.push_back({bx, 1, chunk});
+      for (int chunk : {4, 8, 16, 32, 64}) v.push_back({bx, 1, chunk});
   }
   return v;
 }
