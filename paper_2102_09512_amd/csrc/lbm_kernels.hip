@@ -750,7 +750,9 @@ int default_chunk(int D, const int64_t n[3], int bx, int by) {
 // one MI355X this picks 64 x 4 with 4-plane chunks at 64^3 (2.1x the
 // throughput of 16-plane chunks), 32 x 8 / 16 at 96^3, 64 x 4 / 32 at
 // 128^3, 64 x 8 / 64 at 192^3 and 64 x 8 / 128 at 256^3 (5% faster than
-// 64 x 4 / 256 there).  D2Q9: rows of 128.
+// 64 x 4 / 256 there).  D2Q9: rows of 128, or of 256 from 2048 nodes per row
+// (at 4096^2 FP32 256 x 1 / 32 ran 9% faster than 128 x 1 / 32; at 2048^2
+// the two are within 1%).
 Tile default_tile(int D, int precision, const int64_t n[3], bool caloric) {
   if (D == 3) {
     struct Shape { int bx, by; double w; };
@@ -768,7 +770,8 @@ Tile default_tile(int D, int precision, const int64_t n[3], bool caloric) {
     }
     return best;
   }
-  return Tile{128, 1, default_chunk(D, n, 128, 1)};
+  const int bx = (!caloric && n[0] >= 2048) ? 256 : 128;
+  return Tile{bx, 1, default_chunk(D, n, bx, 1)};
 }
 
 bool tile_supported(int D, int precision, const Tile& t, bool caloric) {
