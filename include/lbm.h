@@ -114,8 +114,11 @@ typedef struct {
    lattice: LBM_D2Q9 or LBM_D3Q27; dims: nx, ny, nz (nz must be 1 for D2Q9);
    gamma > 1 (Eq. (97)); Pr > 0 (Eq. (96)); mu > 0 the dynamic viscosity (at
    T_ref when a power law is set), Eq. (92).  opt may be NULL (defaults).
-   Allocates the two population buffers (2 x 2Q x N values).  Returns
-   LBM_EINVAL before any device work on a bad argument; *out is NULL on error. */
+   Allocates the two population buffers (2 x 2Q x N values).  Limits: each
+   dimension up to 2^30, N below 2^31, and the 2Q values of one march plane
+   (an x-y plane for D3Q27, an x row for D2Q9) below 4 GiB (D3Q27: about
+   9.9 M nodes per plane in FP64, 19.9 M in FP32).  Returns LBM_EINVAL before
+   any device work on a bad argument; *out is NULL on error. */
 int lbm_create(lbm_handle* out, int lattice, const int64_t dims[3], double gamma, double Pr, double mu,
                const lbm_options* opt);
 /* Frees everything the handle owns.  NULL is accepted. */

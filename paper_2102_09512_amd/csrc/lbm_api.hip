@@ -226,6 +226,15 @@ int lbm_create(lbm_handle* out, int lattice, const int64_t dims[3], double gamma
       return fail(LBM_EINVAL, "lbm_create: cv_poly needs cv_poly[0] > 0 and cv_poly[1], cv_poly[2] >= 0 (finite)");
   const int64_t N = dims[0] * dims[1] * dims[2];
   if (N > ((int64_t)1 << 31) - 1024) return fail(LBM_EINVAL, "lbm_create: more than 2^31 nodes");
+  // plane-major layout: per march plane, 2Q in-plane arrays; each array is
+  // 64-element aligned and the arrays are staggered by 64 elements
+  const int64_t plane = lattice == 3 ? dims[0] * dims[1] : dims[0];
+  const int64_t ps = ((plane + 63) / 64) * 64 + 64;
+  const int64_t ms = ps * 2 * (lattice == 2 ? 9 : 27);
+  // The step kernel addresses one march plane through a buffer resource with
+  // 32-bit offsets.
+  if (ms * (int64_t)word_of(opt.precision) >= ((int64_t)1 << 32))
+    return fail(LBM_EINVAL, "lbm_create: one march plane of populations exceeds 4 GiB");
 
   lbm::Tile tile = lbm::default_tile(lattice, opt.precision, dims, caloric);
   if (opt.tile[0] || opt.tile[1] || opt.tile[2]) {
@@ -245,14 +254,9 @@ int lbm_create(lbm_handle* out, int lattice, const int64_t dims[3], double gamma
   c->precision = opt.precision;
   for (int a = 0; a < 3; ++a) c->n[a] = dims[a];
   c->N = N;
-  // plane-major layout: per march plane, 2Q in-plane arrays; each array is
-  // 64-element aligned and the arrays are staggered by 64 elements
-  {
-    const int64_t plane = lattice == 3 ? dims[0] * dims[1] : dims[0];
-    c->nm = (int)(lattice == 3 ? dims[2] : dims[1]);
-    c->ps = ((plane + 63) / 64) * 64 + 64;
-    c->ms = c->ps * 2 * c->Q;
-  }
+  c->nm = (int)(lattice == 3 ? dims[2] : dims[1]);
+  c->ps = ps;
+  c->ms = ms;
   c->gamma = gamma;
   c->Pr = Pr;
   c->mu = mu;

@@ -52,6 +52,8 @@ def test_default_options(lbm):
     ((3, (4, 4, 4), 1.4, 0.0, 0.01), "Pr"),
     ((3, (4, 4, 4), 1.4, 0.7, -1.0), "mu"),
     ((3, (4, 4, 4), 1.4, 0.7, float("nan")), "mu"),
+    ((3, ((1 << 30) + 1, 1, 1), 1.4, 0.7, 0.01), "dims"),       # an axis beyond 2^30 nodes
+    ((3, (2048, 2048, 1024), 1.4, 0.7, 0.01), "2^31 nodes"),    # 32-bit node indices
 ])
 def test_create_rejects_bad_arguments(lbm, args, needle):
     with pytest.raises(lbm.LbmError) as e:
@@ -70,6 +72,7 @@ def test_create_rejects_bad_arguments(lbm, args, needle):
     (dict(cv_poly=(1.5, -1.0, 0.0)), "cv_poly"),
     (dict(cv_poly=(1.5, 5.0, 20.0), tile=(64, 8, 16)), "default launch shape"),
     (dict(tile=(48, 4, 8)), "tile"),
+    (dict(tile=(64, 4, -2)), "tile"),
     (dict(u_ref=(1.5, 0.0, 0.0)), "u_ref"),
     (dict(u_ref=(0.0, float("nan"), 0.0)), "u_ref"),
 ])
@@ -78,6 +81,17 @@ def test_create_rejects_bad_options(lbm, kw, needle):
         lbm.lbm_create(3, (8, 8, 8), 1.4, 0.7, 0.01, **kw)
     assert e.value.code == lbm.LBM_EINVAL
     assert needle in str(e.value)
+
+
+@pytest.mark.parametrize("dims,precision", [
+    ((4096, 4096, 2), "LBM_FP64"),     # 16.8 M nodes per plane x 432 B
+    ((8192, 4096, 2), "LBM_FP32_DEV"),  # 33.6 M nodes per plane x 216 B
+])
+def test_create_rejects_planes_beyond_4_gib(lbm, dims, precision):
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(3, dims, 1.4, 0.7, 0.01, precision=getattr(lbm, precision))
+    assert e.value.code == lbm.LBM_EINVAL
+    assert "4 GiB" in str(e.value)
 
 
 def test_null_handle_calls_fail_cleanly(lbm):
