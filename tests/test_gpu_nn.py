@@ -78,6 +78,34 @@ def test_forward_matches_reference():
     assert e < 3e-2  # bf16 operands (8 significant bits) through four layers
 
 
+def test_forward_at_the_benchmark_size():
+    """The forward in the configuration the benchmark times (64^3, channels
+    5-32-32-32-3, He-normal weights, unit scaling, standard-normal input):
+    every output against the bf16-storage reference."""
+    from paper_2102_09512_amd import corrector as Cr
+
+    lbm = _lbm()
+    w = Cr.Workload()
+    ch, n = list(w.channels), w.n_coarse
+    p = Cr.initial_params(ch, seed=0, last_gain=1.0)
+    x = np.random.default_rng(5).standard_normal((5, n, n, n)).astype(np.float32)
+    print(f"[gpu case] network forward {n}^3, channels {ch}", flush=True)
+    net = lbm.lbm_nn_create(ch, (n, n, n))
+    try:
+        lbm.lbm_nn_set_params(net, p)
+        lbm.lbm_nn_set_scaling(net, np.zeros(5), np.ones(5), np.ones(ch[-1]))
+        yd = torch.zeros((ch[-1], n, n, n), dtype=torch.float32, device="cuda")
+        lbm.lbm_nn_forward(net, torch.from_numpy(x).cuda(), yd)
+        torch.cuda.synchronize()
+        y = yd.cpu().numpy()
+    finally:
+        lbm.lbm_nn_destroy(net)
+    ref16, _ = N.forward(p.astype(np.float64), ch, x.astype(np.float64), store=N.bf16)
+    e16 = _rel(y, ref16)
+    print(f"  forward {n}^3: max error {e16:.2e} against bf16 storage, max |y| {np.abs(ref16).max():.3f}", flush=True)
+    assert e16 < 5e-3
+
+
 def test_loss_and_gradients_match_reference():
     lbm = _lbm()
     shape = (8, 4, 64)
