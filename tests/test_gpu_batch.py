@@ -185,3 +185,92 @@ def test_batch_argument_errors():
     finally:
         lbm.lbm_destroy(h1)
         lbm.lbm_destroy(h2)
+
+
+def test_full_ensemble_in_the_benchmark_configuration():
+    """The benchmark's ensemble (64 D2Q9 boxes of 64^2 .. 512^2, seeds 0..63,
+    FP32, autotuned tile, 50-step graphs, 1000 steps): every box ends bit for
+    bit where lbm_step takes it alone with the same launch tile (another tile
+    changes the rounding, which 1000 steps of turbulence amplify); then, for
+    the largest and the smallest of the boxes that stay finite, one more GPU
+    step from that state against the oracle's step of the
+    same populations (every node whose velocity components are all clear of
+    FP32 rounding around zero, where either upwind side is valid)."""
+    import oracle
+
+    lbm = _lbm()
+    boxes = I.ensemble_2d(64)
+    print(f"[gpu case] full ensemble: {len(boxes)} boxes, "
+          f"{sum(b['dims'][0] * b['dims'][1] for b in boxes)} nodes, 1000 steps", flush=True)
+    prec = lbm.LBM_FP32_DEV
+
+    def make(tile=None):
+        hs = []
+        for b in boxes:
+            h = lbm.lbm_create(2, b["dims"], 1.4, 0.7, b["mu"], precision=prec, visc_exponent=0.76, T_ref=0.15,
+                               tile=tile)
+            lbm.lbm_set_stream(h, torch.cuda.current_stream())
+            lbm.lbm_init_fields(h, *(torch.from_numpy(a).cuda() for a in b["fields"]))
+            hs.append(h)
+        return hs
+
+    bat = make()
+    batch = lbm.lbm_batch_create(bat)
+    ref = []
+    try:
+        lbm.lbm_batch_tune(batch, 5)
+        tile = lbm.lbm_batch_get_tile(batch)
+        print(f"  tuned tile {tile}", flush=True)
+        ref = make(tile)  # chunk 0: each box's default chunk for the shape, as in the batch
+        lbm.lbm_batch_step(batch, 1000, 50)
+        for h in ref:
+            lbm.lbm_step(h, 1000)
+        torch.cuda.synchronize()
+        finite = []
+        for i, (a, b) in enumerate(zip(ref, bat)):
+            nb = lbm.lbm_state_bytes(a) // 4
+            sa = torch.empty(nb, dtype=torch.float32, device="cuda")
+            sb = torch.empty(nb, dtype=torch.float32, device="cuda")
+            lbm.lbm_get_state(a, sa)
+            lbm.lbm_get_state(b, sb)
+            torch.cuda.synchronize()
+            # bit patterns: boxes that left the stable range hold NaNs, which must match too
+            assert torch.equal(sa.view(torch.int32), sb.view(torch.int32)), f"box {i} {boxes[i]['dims']}"
+            finite.append(bool(torch.isfinite(sa).all()))
+        print(f"  {finite.count(False)} of {len(boxes)} boxes left the stable range (the method's limit at this "
+              f"resolution and Mach number, also in the oracle)", flush=True)
+        areas = [b["dims"][0] * b["dims"][1] if ok else 0 for b, ok in zip(boxes, finite)]
+        small = [a if a else 1 << 40 for a in areas]
+        for i in (int(np.argmax(areas)), int(np.argmin(small))):
+            h, (nx, ny) = ref[i], boxes[i]["dims"]
+            nb = lbm.lbm_state_bytes(h) // 4
+            dev = torch.empty(nb, dtype=torch.float32, device="cuda")
+            lbm.lbm_get_state(h, dev)
+            torch.cuda.synchronize()
+            before = dev.cpu().numpy().reshape(18, nx * ny).astype(np.float64)
+            lbm.lbm_step(h, 1)
+            lbm.lbm_get_state(h, dev)
+            torch.cuda.synchronize()
+            after = dev.cpu().numpy().reshape(18, nx * ny).astype(np.float64)
+            rho0, T0 = float(np.float32(1.0)), float(np.float32(0.15))
+            rest = np.concatenate([np.asarray(oracle.feq(2, rho0, [0.0, 0.0, 0.0], T0)),
+                                   np.asarray(oracle.geq(2, rho0, [0.0, 0.0, 0.0], T0, 2.5))])[:, None]
+            s = oracle.Sim(2, (nx, ny), gamma=1.4, Pr=0.7, mu=boxes[i]["mu"], visc_exp=0.76, T_ref=0.15)
+            full = before + rest
+            s.set_pops(full[:9], full[9:], 1000)
+            s.step(1)
+            f_ref, g_ref = s.get_pops()
+            ref_pops = np.concatenate([f_ref.reshape(9, -1), g_ref.reshape(9, -1)]) - rest
+            c = oracle.velocities(2)
+            fr = f_ref.reshape(9, -1)
+            u = (c.T @ fr) / fr.sum(axis=0)
+            keep = np.abs(u[:2]).min(axis=0) > 1e-5
+            assert keep.sum() > 0.99 * keep.size
+            err = np.abs(after - ref_pops)[:, keep] / np.abs(ref_pops).max(axis=1, keepdims=True)
+            print(f"  box {i} {nx}x{ny}: one step from the state after 1000, max error {err.max():.2e} "
+                  f"({int((~keep).sum())} nodes left out)", flush=True)
+            assert err.max() <= 1e-5
+    finally:
+        lbm.lbm_batch_destroy(batch)
+        for h in ref + bat:
+            lbm.lbm_destroy(h)
