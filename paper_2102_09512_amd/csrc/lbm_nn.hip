@@ -66,6 +66,14 @@ constexpr int kW = 8;                   // wavefronts per work-group
 constexpr int kR = kTY * kTZ / kW;      // output rows (32 nodes each) per wavefront
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
 
+// Consecutive hardware work-group ids go round the eight XCDs (each with its
+// own L2); the logical tile order is rebuilt so that every XCD runs one
+// contiguous range of tiles, whose halos then overlap inside that XCD's L2.
+__device__ inline int xcd_tile(int b, int nblocks) {
+  const int q8 = nblocks >> 3, r8 = nblocks & 7, xcd = b & 7;
+  return xcd * q8 + min(xcd, r8) + (b >> 3);
+}
+
 // 16-byte chunk c of the node at halo column hx is stored at chunk
 // c ^ f(hx).  A 16-byte LDS read is served sixteen lanes at a time over 64
 // banks of 4 bytes (256 bytes); sixteen consecutive lanes (consecutive hx,
@@ -94,7 +102,7 @@ __global__ void __launch_bounds__(64 * kW) conv_kernel(const __bf16* __restrict_
   constexpr int CH = CIN / 8;  // 16-byte chunks per node
   __shared__ __attribute__((aligned(16))) __bf16 tile[kHZ * kHY * kHX * CIN];
   const int tx = g.nx / kTX, ty = g.ny / kTY;
-  const int b = blockIdx.x;
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (b % tx) * kTX, y0 = ((b / tx) % ty) * kTY, z0 = (b / (tx * ty)) * kTZ;
   // Staging: every thread issues all its loads before its first LDS write,
   // so the tile costs one memory latency instead of one per chunk.
@@ -217,7 +225,8 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const __bf16* __restrict__ i
 #pragma unroll
   for (int j = 0; j < 8; ++j) ones[j] = (__bf16)1.f;
   f16v acc[7] = {};
-  const int first = blockIdx.x * tpb, last = min(first + tpb, ntiles);
+  const int bl = xcd_tile(blockIdx.x, gridDim.x);  // logical block: tiles and partial slot
+  const int first = bl * tpb, last = min(first + tpb, ntiles);
   for (int tile = first; tile < last; ++tile) {
     const int x0 = (tile % tx) * kGX, y0 = ((tile / tx) % ty) * kGY, z0 = (tile / (tx * ty)) * kGZ;
     __syncthreads();  // every wave is done with the previous tile
@@ -278,7 +287,7 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const __bf16* __restrict__ i
   }
 #pragma unroll
   for (int k = 0; k < 7; ++k) {
-    float* dst = part + ((size_t)(w + 4 * k) * gridDim.x + blockIdx.x) * 1024;
+    float* dst = part + ((size_t)(w + 4 * k) * gridDim.x + bl) * 1024;
 #pragma unroll
     for (int i = 0; i < 16; ++i) dst[(8 * (i >> 2) + 4 * half + (i & 3)) * 32 + r] = acc[k][i];
   }
