@@ -735,10 +735,10 @@ static int64_t best_chunk3(const int64_t n[3], int bx, int by, double w, double*
 
 int default_chunk(int D, const int64_t n[3], int bx, int by) {
   if (D == 3) return (int)best_chunk3(n, bx, by, 1.0, nullptr);
-  // D2Q9: chunks short enough for about 1024 work-groups (the whole 2-D
-  // field is small), between 4 and 32 rows.
+  // D2Q9: chunks short enough for about 2^17 threads in flight (1024
+  // work-groups of 128; the whole 2-D field is small), between 4 and 32 rows.
   const int64_t tiles = (n[0] + bx - 1) / bx;
-  int64_t chunk = n[1] * tiles / 1024;
+  int64_t chunk = n[1] * tiles * bx / (1024 * 128);
   chunk = chunk < 4 ? 4 : (chunk > 32 ? 32 : chunk);
   return (int)(chunk < n[1] ? chunk : n[1]);
 }
@@ -750,9 +750,9 @@ int default_chunk(int D, const int64_t n[3], int bx, int by) {
 // one MI355X this picks 64 x 4 with 4-plane chunks at 64^3 (2.1x the
 // throughput of 16-plane chunks), 32 x 8 / 16 at 96^3, 64 x 4 / 32 at
 // 128^3, 64 x 8 / 64 at 192^3 and 64 x 8 / 128 at 256^3 (5% faster than
-// 64 x 4 / 256 there).  D2Q9: rows of 128, or of 256 from 2048 nodes per row
-// (at 4096^2 FP32 256 x 1 / 32 ran 9% faster than 128 x 1 / 32; at 2048^2
-// the two are within 1%).
+// 64 x 4 / 256 there).  D2Q9: rows of 128, or of 256 from 1024 nodes per row
+// (FP32: 9% faster at 4096^2, even at 1024^2 and 2048^2; FP64 at 1024^2: 4%
+// faster).
 Tile default_tile(int D, int precision, const int64_t n[3], bool caloric) {
   if (D == 3) {
     struct Shape { int bx, by; double w; };
@@ -770,7 +770,7 @@ Tile default_tile(int D, int precision, const int64_t n[3], bool caloric) {
     }
     return best;
   }
-  const int bx = (!caloric && n[0] >= 2048) ? 256 : 128;
+  const int bx = (!caloric && n[0] >= 1024) ? 256 : 128;
   return Tile{bx, 1, default_chunk(D, n, bx, 1)};
 }
 
