@@ -72,6 +72,9 @@ def lib():
         L.orc_init.argtypes = [C.c_void_p, _dp, _dp, _dp]
         L.orc_step.argtypes = [C.c_void_p, C.c_long]
         L.orc_step_sampled.argtypes = [C.c_void_p, C.POINTER(C.c_long), C.c_long, _dp, _dp]
+        L.orc_step_sampled_branch.argtypes = [C.c_void_p, C.POINTER(C.c_long), C.c_long, C.POINTER(C.c_byte),
+                                              _dp, _dp]
+        L.orc_set_fp32_storage.argtypes = [C.c_void_p, _dp, _dp]
         L.orc_step_count.restype = C.c_long
         L.orc_step_count.argtypes = [C.c_void_p]
         L.orc_moments.argtypes = [C.c_void_p, _dp, _dp, _dp]
@@ -275,6 +278,31 @@ class Sim:
         if rc != 0:
             raise MemoryError("oracle: step_sampled failed")
         return f, g
+
+    def step_sampled_branch(self, nodes, branch):
+        """step_sampled with the upwind side forced per node and axis:
+        branch (count, D) of -1 (sign of u), 0 (backward) or 1 (forward)."""
+        nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+        k = nodes.size
+        br = np.ascontiguousarray(branch, dtype=np.int8).reshape(k, self.D)
+        f = np.zeros((Q(self.D), k))
+        g = np.zeros((Q(self.D), k))
+        rc = lib().orc_step_sampled_branch(self._h, nodes.ctypes.data_as(C.POINTER(C.c_long)), k,
+                                           br.ctypes.data_as(C.POINTER(C.c_byte)), _ptr(f), _ptr(g))
+        if rc != 0:
+            raise ValueError("oracle: step_sampled_branch failed")
+        return f, g
+
+    def set_fp32_storage(self, f_ref=None, g_ref=None):
+        """FP32 storage model (see oracle.h); None switches it off."""
+        if f_ref is None:
+            lib().orc_set_fp32_storage(self._h, None, None)
+            return
+        fr = np.ascontiguousarray(f_ref, dtype=np.float64)
+        gr = np.ascontiguousarray(g_ref, dtype=np.float64)
+        assert fr.size == Q(self.D) and gr.size == Q(self.D)
+        if lib().orc_set_fp32_storage(self._h, _ptr(fr), _ptr(gr)) != 0:
+            raise ValueError("oracle: non-finite storage reference")
 
     def moments(self):
         rho = np.zeros(self.shape)

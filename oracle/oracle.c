@@ -60,7 +60,13 @@ struct orc_sim {
   double* Qt;    /* [D][N] diagonal anomaly */
   double* d;     /* [N] scratch for one derivative */
   double* dd;    /* [D][N] derivatives */
+  /* FP32 storage model (orc_set_fp32_storage): reference populations whose
+     deviations are rounded to single precision after init and every step */
+  int fp32_store;
+  double fref[QMAX], gref[QMAX];
 };
+
+static void round_storage(orc_sim* s);
 
 int orc_Q(int D) { return D == 2 ? 9 : 27; }
 
@@ -463,6 +469,7 @@ int orc_init(orc_sim* s, const double* rho, const double* u, const double* T) {
       s->g[(size_t)i * N + n] = ge[i];
     }
   }
+  round_storage(s);
   s->step = 0;
   return 0;
 }
@@ -520,8 +527,10 @@ static void pass1_node(orc_sim* s, long n) {
   }
 }
 
-/* Pass 2 at one node: relaxation with the derivatives already in s->dd. */
-static void pass2_node(const orc_sim* s, long n, double* f_out, long f_stride, double* g_out, long g_stride) {
+/* Pass 2 at one node: relaxation with the derivatives already in s->dd, or
+   with d_in[0..D-1] when d_in is not NULL. */
+static void pass2_node(const orc_sim* s, long n, const double* d_in, double* f_out, long f_stride, double* g_out,
+                       long g_stride) {
   const orc_params* p = &s->p;
   int D = p->D, Q = s->Q;
   long N = s->N;
@@ -533,7 +542,7 @@ static void pass2_node(const orc_sim* s, long n, double* f_out, long f_stride, d
   node_state m;
   node_moments(D, fl, gl, s->cv, &m);
   node_relax_rates(p, &m);
-  for (int a = 0; a < D; ++a) d[a] = s->dd[(size_t)a * N + n];
+  for (int a = 0; a < D; ++a) d[a] = d_in ? d_in[a] : s->dd[(size_t)a * N + n];
   node_collide(D, s->cv, &m, fl, gl, d, fo, go);
   for (int i = 0; i < Q; ++i) {
     f_out[(size_t)i * f_stride] = fo[i];
@@ -548,23 +557,69 @@ static void pass1(orc_sim* s) {
     orc_derivative(s, a, s->Qt + (size_t)a * s->N, s->u + (size_t)a * s->N, s->dd + (size_t)a * s->N);
 }
 
+/* The FP32 storage model: every stored population becomes its reference
+   value plus its deviation from it rounded to single precision. */
+static void round_storage(orc_sim* s) {
+  if (!s->fp32_store) return;
+  long N = s->N;
+#pragma omp parallel for schedule(static)
+  for (long n = 0; n < N; ++n)
+    for (int i = 0; i < s->Q; ++i) {
+      double* f = s->f + (size_t)i * N + n;
+      double* g = s->g + (size_t)i * N + n;
+      *f = s->fref[i] + (double)(float)(*f - s->fref[i]);
+      *g = s->gref[i] + (double)(float)(*g - s->gref[i]);
+    }
+}
+
+int orc_set_fp32_storage(orc_sim* s, const double* f_ref, const double* g_ref) {
+  if (!f_ref || !g_ref) {
+    s->fp32_store = 0;
+    return 0;
+  }
+  for (int i = 0; i < s->Q; ++i) {
+    if (!isfinite(f_ref[i]) || !isfinite(g_ref[i])) return -1;
+    s->fref[i] = f_ref[i];
+    s->gref[i] = g_ref[i];
+  }
+  s->fp32_store = 1;
+  return 0;
+}
+
 int orc_step(orc_sim* s, long nsteps) {
   if (nsteps < 0) return -1;
   long N = s->N;
   for (long k = 0; k < nsteps; ++k) {
     pass1(s);
 #pragma omp parallel for schedule(static)
-    for (long n = 0; n < N; ++n) pass2_node(s, n, s->f + n, N, s->g + n, N);
+    for (long n = 0; n < N; ++n) pass2_node(s, n, NULL, s->f + n, N, s->g + n, N);
+    round_storage(s);
     s->step += 1;
   }
   return 0;
 }
 
-int orc_step_sampled(const orc_sim* s_in, const long* nodes, long count, double* f_out, double* g_out) {
+/* Upwind difference of Qt along an axis at node n on a given side:
+   0 = the backward difference Qt(x) - Qt(x - e), the side Sec. III.A takes
+   when u > 0; 1 = the forward difference Qt(x + e) - Qt(x). */
+static double upwind_side(const orc_sim* s, const double* Qt, long n, int axis, int side) {
+  long np = neighbour(&s->p, n, axis, +1), nm = neighbour(&s->p, n, axis, -1);
+  return side == 0 ? Qt[n] - Qt[nm] : Qt[np] - Qt[n];
+}
+
+int orc_step_sampled_branch(const orc_sim* s_in, const long* nodes, long count, const signed char* branch,
+                            double* f_out, double* g_out) {
   /* Run pass 1 on a private copy of the per-node scratch, then pass 2 at the
      requested nodes only.  The stored populations are not modified. */
+  int D = s_in->p.D;
+  for (long k = 0; k < count; ++k) {
+    if (nodes[k] < 0 || nodes[k] >= s_in->N) return -1;
+    if (branch)
+      for (int a = 0; a < D; ++a)
+        if (branch[k * D + a] < -1 || branch[k * D + a] > 1) return -1;
+  }
   orc_sim tmp = *s_in;
-  size_t NQ = (size_t)s_in->N * s_in->Q, ND = (size_t)s_in->N * s_in->p.D;
+  size_t NQ = (size_t)s_in->N * s_in->Q, ND = (size_t)s_in->N * D;
   tmp.fh = (double*)malloc(NQ * sizeof(double));
   tmp.gh = (double*)malloc(NQ * sizeof(double));
   tmp.rho = (double*)malloc((size_t)s_in->N * sizeof(double));
@@ -575,7 +630,16 @@ int orc_step_sampled(const orc_sim* s_in, const long* nodes, long count, double*
   int ok = tmp.fh && tmp.gh && tmp.rho && tmp.u && tmp.T && tmp.Qt && tmp.dd;
   if (ok) {
     pass1(&tmp);
-    for (long k = 0; k < count; ++k) pass2_node(&tmp, nodes[k], f_out + k, count, g_out + k, count);
+    for (long k = 0; k < count; ++k) {
+      const long node = nodes[k];
+      double d[3] = {0, 0, 0};
+      for (int a = 0; a < D; ++a) {
+        d[a] = tmp.dd[(size_t)a * tmp.N + node];
+        if (branch && branch[k * D + a] >= 0 && tmp.p.deriv == ORC_UPWIND)
+          d[a] = upwind_side(&tmp, tmp.Qt + (size_t)a * tmp.N, node, a, branch[k * D + a]);
+      }
+      pass2_node(&tmp, node, d, f_out + k, count, g_out + k, count);
+    }
   }
   free(tmp.fh);
   free(tmp.gh);
@@ -585,6 +649,10 @@ int orc_step_sampled(const orc_sim* s_in, const long* nodes, long count, double*
   free(tmp.Qt);
   free(tmp.dd);
   return ok ? 0 : -1;
+}
+
+int orc_step_sampled(const orc_sim* s, const long* nodes, long count, double* f_out, double* g_out) {
+  return orc_step_sampled_branch(s, nodes, count, NULL, f_out, g_out);
 }
 
 int orc_moments(const orc_sim* s, double* rho, double* u, double* T) {

@@ -81,6 +81,21 @@ int orc_step(orc_sim* s, long nsteps);
    post-collision populations to f_out[i*count + k], g_out[i*count + k] and
    leaves the state unchanged. */
 int orc_step_sampled(const orc_sim* s, const long* nodes, long count, double* f_out, double* g_out);
+/* orc_step_sampled with the upwind side of the anomaly difference (Sec. III.A)
+   at sampled node k forced on the axes where branch[k*D + a] is 0 (backward
+   difference Qt(x) - Qt(x - e_a), the side taken when u_a > 0) or 1 (forward
+   difference Qt(x + e_a) - Qt(x)); -1 leaves the choice to the sign of u_a.
+   branch may be NULL.  Ignored for the central variant.  Returns -1 on a node
+   index outside the field or a branch value outside -1..1. */
+int orc_step_sampled_branch(const orc_sim* s, const long* nodes, long count, const signed char* branch,
+                            double* f_out, double* g_out);
+/* FP32 storage model: from now on, after orc_init and after every step, each
+   population becomes ref_i + (double)(float)(value - ref_i), the value that a
+   single-precision store of its deviation from the reference populations
+   f_ref[Q], g_ref[Q] keeps (the arithmetic stays FP64).  This measures what
+   FP32 deviation storage alone costs a flow.  NULL pointers switch it off.
+   Returns -1 on a non-finite reference value. */
+int orc_set_fp32_storage(orc_sim* s, const double* f_ref, const double* g_ref);
 long orc_step_count(const orc_sim* s);
 /* Moments of the stored populations (no streaming). */
 int orc_moments(const orc_sim* s, double* rho, double* u, double* T);

@@ -15,7 +15,9 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
-PINS = [os.path.join(ROOT, "tests", "test_oracle_equilibria.py"),
+PINS = [os.path.join(ROOT, "tests", "test_oracle_diagnostics.py"),
+        os.path.join(ROOT, "tests", "test_oracle_sampled.py"),
+        os.path.join(ROOT, "tests", "test_oracle_equilibria.py"),
         os.path.join(ROOT, "tests", "test_oracle_physics.py"),
         os.path.join(ROOT, "tests", "test_oracle_caloric.py")]
 
@@ -44,6 +46,35 @@ MUTANTS = [
     ("newton_step_sign", "    T -= dT;", "    T += dT;"),
     ("geq_ignores_caloric_law", "double s = U;", "double s = 2.5 * T;"),
     ("sound_speed_gamma_inverted", "gam = (cvT + 1.0) / cvT;", "gam = cvT / (cvT + 1.0);"),
+    # diagnostics (Eqs. (3)-(5), Sec. III.D statistics)
+    ("kinetic_energy_doubled", "c[(size_t)ORC_D_KINETIC * N] = 0.5 * rho[n] * uu;",
+     "c[(size_t)ORC_D_KINETIC * N] = rho[n] * uu;"),
+    ("diagnostic_central_half_dropped",
+     "return 0.5 * (F[neighbour(&s->p, n, axis, +1)] - F[neighbour(&s->p, n, axis, -1)]);",
+     "return (F[neighbour(&s->p, n, axis, +1)] - F[neighbour(&s->p, n, axis, -1)]);"),
+    ("curl_z_sign", "gz = central(s, u + (size_t)N, n, 0) - central(s, u, n, 1);",
+     "gz = central(s, u + (size_t)N, n, 0) + central(s, u, n, 1);"),
+    ("curl_x_sign", "gx = central(s, u + 2 * (size_t)N, n, 1) - central(s, u + (size_t)N, n, 2);",
+     "gx = central(s, u + 2 * (size_t)N, n, 1) + central(s, u + (size_t)N, n, 2);"),
+    ("curl_y_wrong_axis", "gy = central(s, u, n, 2) - central(s, u + 2 * (size_t)N, n, 0);",
+     "gy = central(s, u, n, 1) - central(s, u + 2 * (size_t)N, n, 0);"),
+    ("dilatation_last_axis_only", "div += du[a];", "div = du[a];"),
+    ("dissipation_constant_mu", "c[(size_t)ORC_D_DISS * N] = viscosity(p, T[n]) * vort2;",
+     "c[(size_t)ORC_D_DISS * N] = p->mu0 * vort2;"),
+    ("rho2_not_squared", "c[(size_t)ORC_D_RHO2 * N] = rho[n] * rho[n];", "c[(size_t)ORC_D_RHO2 * N] = rho[n];"),
+    ("u_axis_slot_index", "c[(size_t)ORC_D_UY2 * N] = uy * uy;", "c[(size_t)ORC_D_UY2 * N] = ux * ux;"),
+    ("du_axis_slot_index", "c[(size_t)ORC_D_DUY2 * N] = du[1] * du[1];", "c[(size_t)ORC_D_DUY2 * N] = du[0] * du[0];"),
+    ("nonpositive_ignores_rho", "(rho[n] <= 0.0 || T[n] <= 0.0)", "(T[n] <= 0.0)"),
+    # sampled step, upwind-side override, FP32 storage model
+    ("override_sides_swapped", "return side == 0 ? Qt[n] - Qt[nm] : Qt[np] - Qt[n];",
+     "return side == 1 ? Qt[n] - Qt[nm] : Qt[np] - Qt[n];"),
+    ("sampled_step_list_index", "pass2_node(&tmp, node, d, f_out + k, count, g_out + k, count);",
+     "pass2_node(&tmp, k % tmp.N, d, f_out + k, count, g_out + k, count);"),
+    ("sampled_step_derivative_axis", "d[a] = tmp.dd[(size_t)a * tmp.N + node];",
+     "d[a] = tmp.dd[(size_t)(D - 1 - a) * tmp.N + node];"),
+    ("storage_not_rounded", "*f = s->fref[i] + (double)(float)(*f - s->fref[i]);",
+     "*f = s->fref[i] + (*f - s->fref[i]);"),
+    ("storage_not_rounded_at_init", "  round_storage(s);\n  s->step = 0;", "  s->step = 0;"),
 ]
 
 
