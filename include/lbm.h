@@ -77,7 +77,8 @@ typedef struct {
   double rho_ref;       /* reference density of FP32 deviations; default 1 */
   int deriv_scheme;     /* LBM_DERIV_UPWIND (default) or LBM_DERIV_CENTRAL */
   int tile[3];          /* launch shape of the step kernel: x width, y width (D3Q27), march chunk; 0 = default
-                           (a zero chunk with a given shape: the default chunk for that shape) */
+                           (a zero chunk with a given shape: the default chunk for that shape).  Shapes:
+                           D3Q27 64x4, 32x8 and, for LBM_FP32_DEV only, 64x8; D2Q9 64, 128, 256 wide */
   double u_ref[3];      /* reference velocity of FP32 deviations (|u_ref_a| < 1); default 0 */
   double cv_poly[3];    /* caloric law (Sec. II.A, Eq. (6)): C_v(T) = cv_poly[0] + cv_poly[1] T + cv_poly[2] T^2,
                            U(T) = its integral from 0, T recovered from U by Newton's method; needs
@@ -89,8 +90,17 @@ typedef struct {
 void lbm_default_options(lbm_options* opt);
 
 /* Whole-field sums of the stored state (the post-collision populations;
-   moments without streaming).  Derivatives are central differences with the
-   same wrap/clamp rule as the method. */
+   moments without streaming, Eqs. (3)-(7)).  mass, momentum and energy are
+   the conserved totals of Eqs. (3)-(5); the others are the turbulence
+   statistics of Sec. III.D: the kinetic energy, the dilatation (whose mean
+   square gives the rms dilatation), the vorticity (enstrophy = half its mean
+   square) and the dissipation sum mu(T) |curl u|^2 with the viscosity law of
+   Sec. III.D, the velocity and sound-speed sums of the turbulent Mach
+   number, and per-axis variances of the velocity and of its gradient (the
+   Taylor microscale).  Derivatives are central differences with the same
+   wrap/clamp rule as the method.  Every sum is FP64 in a fixed order (wave64
+   shuffles, then per-work-group partials, then one fixed-order pass), so a
+   repeated call gives the same bits. */
 typedef struct {
   int64_t step;
   int64_t nodes;
@@ -126,6 +136,8 @@ int lbm_destroy(lbm_handle h);
 /* Binds a hipStream_t for all later work of this handle. */
 int lbm_set_stream(lbm_handle h, void* hip_stream);
 /* Sets f = f^eq(rho,u,T) (Eq. (20)) and g = g^eq(rho,u,T) (Eq. (42)), step = 0.
+   The equilibria are evaluated in FP64 for either storage (FP32 storage then
+   holds each deviation from the reference state rounded once).
    LBM_EINVAL if any value is non-finite or rho <= 0 or T <= 0 (nothing is
    changed then).  mem: LBM_HOST or LBM_DEVICE. */
 int lbm_init_fields(lbm_handle h, const double* rho, const double* u, const double* T, int mem);
@@ -136,7 +148,13 @@ int lbm_step(lbm_handle h, int64_t n);
 /* rho, u, T of the stored populations (Eqs. (3)-(7) without streaming).  Any
    output pointer may be NULL. */
 int lbm_moments(lbm_handle h, double* rho, double* u, double* T, int mem);
-/* Synchronous reductions over the stored state (FP64, fixed order). */
+/* Synchronous reductions over the stored state (FP64, fixed order) into
+   *out (host): the totals of Eqs. (3)-(5) and the statistics of Sec. III.D
+   listed at lbm_diag.  Sets the handle's instability flag when a node is
+   non-finite or has rho <= 0 or T <= 0 (lbm_step then returns
+   LBM_EUNSTABLE).  Allocates a 6 N-double field buffer and the partial sums
+   on first use.  LBM_EINVAL on a NULL argument, LBM_ESTATE before
+   lbm_init_fields. */
 int lbm_diagnostics(lbm_handle h, lbm_diag* out);
 /* Raw state for checkpoints: 2Q population planes of N values (f then g) in
    the storage type (FP64: double values; FP32_DEV: float deviations). */
@@ -146,6 +164,9 @@ int lbm_get_state(lbm_handle h, void* buf, size_t bytes, int mem);
    dims and precision; the step counter is set to step. */
 int lbm_set_state(lbm_handle h, const void* buf, size_t bytes, int mem, int64_t step);
 int64_t lbm_step_count(lbm_handle h);
+/* Lattice (LBM_D2Q9 or LBM_D3Q27) and dims {nx, ny, nz} of a handle, as
+   given to lbm_create (host outputs).  LBM_EINVAL on a NULL argument. */
+int lbm_get_dims(lbm_handle h, int* lattice, int64_t dims[3]);
 /* Launch tile {bx, by, chunk} of the handle's step kernel (the default chosen
    at lbm_create, or lbm_options.tile).  LBM_EINVAL on a NULL argument. */
 int lbm_get_tile(lbm_handle h, int tile[3]);

@@ -412,6 +412,13 @@ int lbm_diagnostics(lbm_handle h, lbm_diag* out) {
   return LBM_OK;
 }
 
+int lbm_get_dims(lbm_handle h, int* lattice, int64_t dims[3]) {
+  if (!h || !lattice || !dims) return fail(LBM_EINVAL, "lbm_get_dims: NULL argument");
+  *lattice = h->lattice;
+  for (int a = 0; a < 3; ++a) dims[a] = h->n[a];
+  return LBM_OK;
+}
+
 int lbm_get_tile(lbm_handle h, int tile[3]) {
   if (!h || !tile) return fail(LBM_EINVAL, "lbm_get_tile: NULL argument");
   tile[0] = h->tile.bx;

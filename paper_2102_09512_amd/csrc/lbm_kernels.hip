@@ -472,14 +472,16 @@ __global__ void __launch_bounds__(64) toggle_cur_kernel(BoxEntry* __restrict__ t
 }
 
 // ---------------------------------------------------------------------------
-// Initialisation: f = f^eq, g = g^eq (minus the rest state when DEV)
+// Initialisation: f = f^eq, g = g^eq (minus the reference state when DEV).
+// The equilibria are evaluated in FP64 for either storage, so FP32 storage
+// holds each deviation rounded once.
 // ---------------------------------------------------------------------------
 
 template <int D, bool DEV, typename S>
 __global__ void __launch_bounds__(256) init_kernel(const double* __restrict__ rho, const double* __restrict__ u,
                                                    const double* __restrict__ T, S* __restrict__ dst, long long N,
                                                    const StepParams p) {
-  using R = typename StoreOf<S>::R;
+  using R = double;
   constexpr int Q = lat_q(D);
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
@@ -774,10 +776,14 @@ Tile default_tile(int D, int precision, const int64_t n[3], bool caloric) {
   return Tile{bx, 1, default_chunk(D, n, bx, 1)};
 }
 
+// The 512-thread 64 x 8 shape exists for FP32 storage only: with FP64
+// populations it does not fit the registers of two wavefronts per SIMD and
+// spills, so it is not compiled for FP64.
 bool tile_supported(int D, int precision, const Tile& t, bool caloric) {
-  (void)precision;
   if (caloric) return D == 3 ? (t.bx == 64 && t.by == 4) : (t.bx == 128 && t.by == 1);
-  if (D == 3) return (t.bx == 64 && (t.by == 4 || t.by == 8)) || (t.bx == 32 && t.by == 8);
+  if (D == 3)
+    return (t.bx == 64 && t.by == 4) || (t.bx == 32 && t.by == 8) ||
+           (t.bx == 64 && t.by == 8 && precision == LBM_FP32_DEV);
   return t.by == 1 && (t.bx == 64 || t.bx == 128 || t.bx == 256);
 }
 
@@ -794,7 +800,8 @@ static hipError_t dispatch_tile(const Ctx& c, const void* src, void* dst) {
   }
   if constexpr (D == 3) {
     if (t.bx == 64 && t.by == 4) return launch_step_t<D, DEV, S, 64, 4>(c, src, dst);
-    if (t.bx == 64 && t.by == 8) return launch_step_t<D, DEV, S, 64, 8>(c, src, dst);
+    if constexpr (DEV)
+      if (t.bx == 64 && t.by == 8) return launch_step_t<D, DEV, S, 64, 8>(c, src, dst);
     if (t.bx == 32 && t.by == 8) return launch_step_t<D, DEV, S, 32, 8>(c, src, dst);
   } else {
     if (t.bx == 64) return launch_step_t<D, DEV, S, 64, 1>(c, src, dst);
@@ -825,7 +832,8 @@ static hipError_t dispatch_batch(const Batch& b, hipStream_t s, int flip) {
   const Tile& t = b.tile;
   if constexpr (D == 3) {
     if (t.bx == 64 && t.by == 4) return launch_batch_t<D, DEV, S, 64, 4>(b, s, flip);
-    if (t.bx == 64 && t.by == 8) return launch_batch_t<D, DEV, S, 64, 8>(b, s, flip);
+    if constexpr (DEV)
+      if (t.bx == 64 && t.by == 8) return launch_batch_t<D, DEV, S, 64, 8>(b, s, flip);
     if (t.bx == 32 && t.by == 8) return launch_batch_t<D, DEV, S, 32, 8>(b, s, flip);
   } else {
     if (t.bx == 64) return launch_batch_t<D, DEV, S, 64, 1>(b, s, flip);

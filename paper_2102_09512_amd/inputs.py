@@ -327,3 +327,29 @@ def linear_wave(D, n, kind, eps=1e-4, rho0=1.0, T0=0.15, U=0.0, gamma=1.4, mode=
     else:
         raise ValueError(kind)
     return rho, u, T
+
+
+class PopulationPerturbation:
+    """Seeded smooth periodic perturbations of raw population arrays, one
+    row (a population) at a time: row i is
+        amp * cos(k_x x + a) cos(k_y y + b) cos(k_z z + c)
+    with wave numbers of 1 to 3 periods per axis and phases drawn from
+    (seed, i).  Added to the stored populations of an initial state it gives a
+    generic non-equilibrium state for one-step parity checks; it is plain
+    random input, independent of the method's arithmetic."""
+
+    def __init__(self, dims, seed, amp):
+        self.dims = tuple(int(d) for d in dims) + (1,) * (3 - len(dims))
+        self.seed = int(seed)
+        self.amp = float(amp)
+
+    def row(self, i) -> np.ndarray:
+        """Row i as a flat FP64 array in node order (x fastest)."""
+        r = np.random.default_rng((self.seed, int(i)))
+        nx, ny, nz = self.dims
+        fac = []
+        for n in (nx, ny, nz):
+            k = 2.0 * math.pi * int(r.integers(1, 4)) / n
+            fac.append(np.cos(k * np.arange(n) + r.uniform(0.0, 2.0 * math.pi)))
+        out = self.amp * fac[2][:, None, None] * fac[1][None, :, None] * fac[0][None, None, :]
+        return out.reshape(-1)

@@ -108,12 +108,13 @@ def _load():
     L.lbm_batch_set_tile.argtypes = [vp, C.POINTER(C.c_int)]
     L.lbm_batch_get_tile.argtypes = [vp, C.POINTER(C.c_int)]
     L.lbm_get_tile.argtypes = [vp, C.POINTER(C.c_int)]
+    L.lbm_get_dims.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(i64)]
     L.lbm_batch_tune.argtypes = [vp, C.c_int, dp]
     L.lbm_batch_step.argtypes = [vp, i64, C.c_int]
     for name in ("lbm_create", "lbm_destroy", "lbm_set_stream", "lbm_init_fields", "lbm_step", "lbm_moments",
                  "lbm_diagnostics", "lbm_get_state", "lbm_set_state", "lbm_device_copy", "lbm_batch_create",
                  "lbm_batch_destroy", "lbm_batch_set_stream", "lbm_batch_set_tile", "lbm_batch_get_tile",
-                 "lbm_get_tile", "lbm_batch_tune", "lbm_batch_step", "lbm_fields_add", "lbm_filter_moments", "lbm_nn_create",
+                 "lbm_get_tile", "lbm_get_dims", "lbm_batch_tune", "lbm_batch_step", "lbm_fields_add", "lbm_filter_moments", "lbm_nn_create",
                  "lbm_nn_destroy", "lbm_nn_set_stream", "lbm_nn_set_params", "lbm_nn_get_params", "lbm_nn_get_grads",
                  "lbm_nn_zero_grad", "lbm_nn_set_scaling", "lbm_nn_forward", "lbm_nn_loss_backward",
                  "lbm_nn_adam_step", "lbm_nn_take_loss", "lbm_nn_correct", "lbm_nn_fields_to_planes", "lbm_fields_set",
@@ -156,6 +157,37 @@ def _arg(x, dtype=np.float64):
         return x.ctypes.data, LBM_HOST, x
     a = np.ascontiguousarray(x, dtype=dtype)
     return a.ctypes.data, LBM_HOST, a
+
+
+# Shapes of the handles and networks made through this module, so that array
+# sizes are checked before a pointer reaches the library (the C ABI takes
+# plain pointers and cannot).  Handles made elsewhere are asked for their dims.
+_HANDLES: dict = {}
+_NETS: dict = {}
+
+
+def _numel(x) -> int:
+    return int(x.numel()) if _is_torch(x) else int(np.asarray(x).size)
+
+
+def _nodes(h):
+    """(D, N) of a handle."""
+    if h not in _HANDLES:
+        lat, dims = lbm_get_dims(h)
+        _HANDLES[h] = (lat, int(np.prod(dims)))
+    return _HANDLES[h]
+
+
+def _expect(call, name, x, n):
+    if x is not None and _numel(x) != n:
+        raise ValueError(f"{call}: {name} has {_numel(x)} values, expected {n}")
+
+
+def _fields_sized(call, h, rho, u, T):
+    D, N = _nodes(h)
+    _expect(call, "rho", rho, N)
+    _expect(call, "u", u, D * N)
+    _expect(call, "T", T, N)
 
 
 def _same_kind(*kinds):
@@ -202,11 +234,20 @@ def lbm_create(lattice, dims, gamma, Pr, mu, options: lbm_options | None = None,
     d = (C.c_int64 * 3)(*[int(v) for v in (list(dims) + [1] * (3 - len(dims)))])
     h = C.c_void_p()
     _check(_L.lbm_create(C.byref(h), int(lattice), d, float(gamma), float(Pr), float(mu), C.byref(o)))
+    _HANDLES[h.value] = (int(lattice), int(d[0]) * int(d[1]) * int(d[2]))
     return h.value
 
 
 def lbm_destroy(h) -> int:
+    _HANDLES.pop(h, None)
     return _check(_L.lbm_destroy(h))
+
+
+def lbm_get_dims(h):
+    """(lattice, (nx, ny, nz)) of a handle."""
+    lat, d = C.c_int(), (C.c_int64 * 3)()
+    _check(_L.lbm_get_dims(h, C.byref(lat), d))
+    return lat.value, tuple(int(v) for v in d)
 
 
 def lbm_set_stream(h, stream) -> int:
@@ -217,6 +258,7 @@ def lbm_set_stream(h, stream) -> int:
 
 
 def lbm_init_fields(h, rho, u, T) -> int:
+    _fields_sized("lbm_init_fields", h, rho, u, T)
     pr, kr, _kr = _arg(rho)
     pu, ku, _ku = _arg(u)
     pt, kt, _kt = _arg(T)
@@ -229,6 +271,7 @@ def lbm_step(h, n: int = 1) -> int:
 
 def lbm_moments(h, rho=None, u=None, T=None):
     """Writes into the given arrays (numpy or device tensors) and returns them."""
+    _fields_sized("lbm_moments", h, rho, u, T)
     args = [_arg(x) for x in (rho, u, T)]
     kind = _same_kind(*[a[1] for a in args])
     if kind == LBM_HOST:
@@ -338,6 +381,7 @@ def lbm_batch_step(b, n: int = 1, graph_steps: int = 0) -> int:
 # ---- coupling of coarse runs and the learned corrector ---------------------------
 
 def lbm_fields_add(h, drho, du, dT) -> int:
+    _fields_sized("lbm_fields_add", h, drho, du, dT)
     pr, kr, _a = _arg(drho)
     pu, ku, _b = _arg(du)
     pt, kt, _c = _arg(dT)
@@ -345,6 +389,7 @@ def lbm_fields_add(h, drho, du, dT) -> int:
 
 
 def lbm_fields_set(h, rho, u, T) -> int:
+    _fields_sized("lbm_fields_set", h, rho, u, T)
     pr, kr, _a = _arg(rho)
     pu, ku, _b = _arg(u)
     pt, kt, _c = _arg(T)
@@ -353,6 +398,17 @@ def lbm_fields_set(h, rho, u, T) -> int:
 
 def lbm_filter_moments(h, factor, rho, u, T):
     """Writes the coarse moments into rho, u, T (numpy arrays or device tensors)."""
+    D, N = _nodes(h)
+    f = int(factor)
+    if f < 1:
+        raise ValueError("lbm_filter_moments: factor must be >= 1")
+    Nc = N // (f ** D)
+    for name, x, n in (("rho", rho, Nc), ("u", u, D * Nc), ("T", T, Nc)):
+        if x is None:
+            raise ValueError(f"lbm_filter_moments: {name} is required")
+        _expect("lbm_filter_moments", name, x, n)
+        if not _is_torch(x) and not (isinstance(x, np.ndarray) and x.dtype == np.float64 and x.flags.c_contiguous):
+            raise TypeError("host outputs must be C-contiguous float64 numpy arrays")
     args = [_arg(x) for x in (rho, u, T)]
     kind = _same_kind(*[a[1] for a in args])
     _check(_L.lbm_filter_moments(h, int(factor), args[0][0], args[1][0], args[2][0], kind))
@@ -372,11 +428,23 @@ def lbm_nn_create(channels, dims) -> int:
     d = (C.c_int64 * 3)(*[int(v) for v in (list(dims) + [1] * (3 - len(dims)))])
     n = C.c_void_p()
     _check(_L.lbm_nn_create(C.byref(n), len(channels) - 1, ch, d))
+    _NETS[n.value] = (tuple(int(c) for c in channels), int(d[0]) * int(d[1]) * int(d[2]))
     return n.value
 
 
 def lbm_nn_destroy(n) -> int:
+    _NETS.pop(n, None)
     return _check(_L.lbm_nn_destroy(n))
+
+
+def _net_planes(call, n, **arrays):
+    """Checks planar network tensors: name=(array, which) with which 'in'
+    (c[0] planes) or 'out' (c[L] planes)."""
+    if n not in _NETS:
+        return
+    ch, V = _NETS[n]
+    for name, (x, which) in arrays.items():
+        _expect(call, name, x, (ch[0] if which == "in" else ch[-1]) * V)
 
 
 def lbm_nn_set_stream(n, stream) -> int:
@@ -390,6 +458,7 @@ def lbm_nn_param_count(n) -> int:
 
 
 def lbm_nn_set_params(n, params) -> int:
+    _expect("lbm_nn_set_params", "params", params, lbm_nn_param_count(n))
     p, k, _keep = _f32(params)
     return _check(_L.lbm_nn_set_params(n, p, k))
 
@@ -429,6 +498,7 @@ def lbm_nn_set_correction_limit(n, limit: float) -> int:
 
 def lbm_nn_forward(n, x, y) -> int:
     """x, y: contiguous float32 device tensors (planes)."""
+    _net_planes("lbm_nn_forward", n, x=(x, "in"), y=(y, "out"))
     px, kx, _a = _arg(x, dtype=np.float32)
     py, ky, _b = _arg(y, dtype=np.float32)
     if kx != LBM_DEVICE or ky != LBM_DEVICE:
@@ -439,6 +509,7 @@ def lbm_nn_forward(n, x, y) -> int:
 def lbm_nn_loss_backward(n, x, target, sync: bool = True):
     """The sample's loss (synchronous), or None with sync False: the loss is
     then added to the device-side sum that lbm_nn_take_loss returns."""
+    _net_planes("lbm_nn_loss_backward", n, x=(x, "in"), target=(target, "in"))
     px, kx, _a = _arg(x, dtype=np.float32)
     pt, kt, _b = _arg(target, dtype=np.float32)
     if kx != LBM_DEVICE or kt != LBM_DEVICE:

@@ -136,3 +136,70 @@ def test_coupling_null_arguments_fail_cleanly(lbm):
     assert L.lbm_nn_destroy(None) == lbm.LBM_OK
     assert L.lbm_nn_correct(None, None) == lbm.LBM_EINVAL
     assert L.lbm_nn_param_count(None) == -1
+
+
+def test_create_refuses_the_fp64_512_thread_tile(lbm):
+    """64 x 8 tiles exist for FP32 storage only (FP64 would spill registers)."""
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(3, (64, 16, 8), 1.4, 0.7, 0.01, tile=(64, 8, 8))
+    assert e.value.code == lbm.LBM_EINVAL and "tile" in str(e.value)
+
+
+def test_get_dims_null_arguments(lbm):
+    L = lbm.raw()
+    assert L.lbm_get_dims(None, None, None) == lbm.LBM_EINVAL
+
+
+# The binding checks array sizes against the handle's node count before a
+# pointer reaches the library.  A handle the module has registered is enough
+# to exercise that check without a GPU: no library call is made.
+FAKE_H = 0x7FFF0001
+FAKE_NET = 0x7FFF0002
+
+
+@pytest.fixture
+def fake_handles(lbm):
+    lbm._HANDLES[FAKE_H] = (3, 4 * 3 * 2)
+    lbm._NETS[FAKE_NET] = ((5, 32, 3), 32 * 4 * 4)
+    yield
+    lbm._HANDLES.pop(FAKE_H, None)
+    lbm._NETS.pop(FAKE_NET, None)
+
+
+@pytest.mark.parametrize("call", ["lbm_init_fields", "lbm_moments", "lbm_fields_add", "lbm_fields_set"])
+@pytest.mark.parametrize("bad", ["rho", "u", "T"])
+def test_field_arrays_of_the_wrong_size_are_refused(lbm, fake_handles, call, bad):
+    import numpy as np
+
+    N = 24
+    arrays = {"rho": np.ones(N), "u": np.zeros(3 * N), "T": np.full(N, 0.15)}
+    arrays[bad] = np.ones(arrays[bad].size - 1)
+    with pytest.raises(ValueError) as e:
+        getattr(lbm, call)(FAKE_H, arrays["rho"], arrays["u"], arrays["T"])
+    assert bad in str(e.value)
+
+
+def test_filter_outputs_of_the_wrong_size_are_refused(lbm, fake_handles):
+    import numpy as np
+
+    lbm._HANDLES[FAKE_H] = (3, 4 * 4 * 4)  # 4^3 -> 2^3 with factor 2
+    with pytest.raises(ValueError) as e:
+        lbm.lbm_filter_moments(FAKE_H, 2, np.zeros(8), np.zeros(3 * 8 - 1), np.zeros(8))
+    assert "u" in str(e.value)
+    with pytest.raises(ValueError):
+        lbm.lbm_filter_moments(FAKE_H, 2, np.zeros(64), np.zeros(3 * 64), np.zeros(64))
+
+
+def test_network_planes_of_the_wrong_size_are_refused(lbm, fake_handles):
+    import numpy as np
+
+    V = 32 * 4 * 4
+    with pytest.raises(ValueError) as e:
+        lbm.lbm_nn_forward(FAKE_NET, np.zeros(5 * V - 1, dtype=np.float32), np.zeros(3 * V, dtype=np.float32))
+    assert "x" in str(e.value)
+    with pytest.raises(ValueError) as e:
+        lbm.lbm_nn_forward(FAKE_NET, np.zeros(5 * V, dtype=np.float32), np.zeros(5 * V, dtype=np.float32))
+    assert "y" in str(e.value)
+    with pytest.raises(ValueError) as e:
+        lbm.lbm_nn_loss_backward(FAKE_NET, np.zeros(5 * V, dtype=np.float32), np.zeros(3 * V, dtype=np.float32))
+    assert "target" in str(e.value)

@@ -39,7 +39,9 @@ def test_training_lowers_the_loss_and_generalises(trained):
 
 def test_corrected_run_beats_the_plain_coarse_run(trained):
     """On held-out seeds the corrected 32^3 run's kinetic-energy spectrum is
-    closer to the filtered 128^3 run than the plain 32^3 run's."""
+    closer to the filtered 128^3 run than the plain 32^3 run's, and closer
+    than the best plain run (32^3, 40^3 or 48^3) that takes no more wall time
+    than the corrected run (the plain run at equal wall time)."""
     from paper_2102_09512_amd import corrector as Cr
 
     w, res = trained
@@ -49,3 +51,5 @@ def test_corrected_run_beats_the_plain_coarse_run(trained):
     s = Cr.summarize(rows)
     print("  summary", s, flush=True)
     assert s["learned"] < s["plain_coarse"]
+    assert s["learned"] < s["plain_equal_time"]
+    assert s["wins_equal_time"] == s["seeds"]

@@ -2,11 +2,10 @@
 
 The fused step keeps two planes of 27 (f, g) pairs in flight per thread, so
 its register budget is tight: a spill to scratch memory costs far more than
-the arithmetic it saves.  Every instantiation that the default launch shape
-or the batch autotuner can pick must use no scratch; the one exception is
-FP64 storage with the 512-thread 64 x 8 shape, which the defaults never
-choose (it exists only as an explicit option).  Compiles the kernel source
-for gfx950 on the host (device code only, about half a minute)."""
+the arithmetic it saves.  Every compiled instantiation must use no scratch
+(the 512-thread 64 x 8 shape exists for FP32 storage only: with FP64
+populations it would spill, so it is not compiled).  Compiles the kernel
+source for gfx950 on the host (device code only, about half a minute)."""
 import os
 import re
 import shutil
@@ -51,9 +50,8 @@ def test_step_kernels_do_not_spill(tmp_path):
             continue
         D, _, S, bx, by = m.groups()
         seen += 1
-        if D == "3" and S == "d" and (bx, by) == ("64", "8"):
-            continue  # explicit option only
+        assert not (D == "3" and S == "d" and (bx, by) == ("64", "8")), name
         assert res.get("ScratchSize [bytes/lane]", -1) == 0, (name, res)
         if (D, S, bx, by) == ("3", "f", "64", "8"):
             assert res.get("Occupancy [waves/SIMD]", 0) >= 2, (name, res)
-    assert seen >= 20, f"only {seen} step kernels found"
+    assert seen >= 18, f"only {seen} step kernels found"
