@@ -36,8 +36,15 @@ bf16 matrix-core roofline of the convolution kernels, for profiling.
 One timed step = one lbm_step (one launch of the fused kernel) over the whole
 box; the diagnostics reduction runs every --diag-every steps inside the timed
 region.  Prints one JSON line (metric MLUPS) with the roofline of the step
-kernel (algorithmic bytes per node update 2 x Q x (read + write) x word) and
-the CPU oracle timed on a bounded sample of the same workload.
+kernel (algorithmic bytes per node update 2 x Q x (read + write) x word),
+the library's access-pattern reference of the step kernel (the same loads and
+stores without the collision: the ceiling of this access pattern) and its
+copy kernel, and the CPU oracle timed on a bounded sample of the same
+workload.  For the default 256^3 turbulence workload the line also carries
+the second half of the benchmark's metric, "learned_corrector": the learned
+coarse-grid corrector trained for --learned-epochs epochs (fixed, independent
+of --steps) and its kinetic-energy spectrum error against the plain method at
+equal wall time (as in --workload learned64; --no-learned skips it).
 """
 from __future__ import annotations
 
@@ -209,20 +216,20 @@ def run_ensemble(args, torch, lbm, dev):
     return out
 
 
-def run_learned(args, torch, lbm, dev):
-    """The learned workload (see the module docstring)."""
-    import numpy as np
-
+def learned_evaluation(torch, lbm, dev, epochs, train_seeds, eval_seeds, lr):
+    """Trains the corrector for a fixed number of epochs and compares the
+    corrected 64^3 run with plain runs at equal wall time (see the module
+    docstring).  Returns (summary rows, training result, extras)."""
     from paper_2102_09512_amd import corrector as Cr
 
     w = Cr.Workload()
-    tr = Cr.training_seeds(args.train_seeds)
-    ev = Cr.evaluation_seeds(args.eval_seeds)
+    tr = Cr.training_seeds(train_seeds)
+    ev = Cr.evaluation_seeds(eval_seeds)
     t0 = time.perf_counter()
     pairs = Cr.generate_pairs(w, *tr, log=_log)
     t_data = time.perf_counter() - t0
     n_pairs = int(pairs.shape[0])
-    res = Cr.train(w, pairs, epochs=args.steps, lr=args.lr, batch=4, log=_log)
+    res = Cr.train(w, pairs, epochs=epochs, lr=lr, batch=4, log=_log)
     del pairs
     vp = Cr.generate_pairs(w, *ev, log=_log)
     zero_loss = Cr.no_correction_loss(w, vp, res.scaling[2])
@@ -245,18 +252,59 @@ def run_learned(args, torch, lbm, dev):
     e1.record(stream)
     torch.cuda.synchronize()
     fwd_s = e0.elapsed_time(e1) / 1e3 / reps
-    ch = w.channels
-    flops = sum(2 * 27 * ch[l] * ch[l + 1] for l in range(len(ch) - 1)) * V
-    tflops = flops / fwd_s / 1e12
     lbm.lbm_nn_set_stream(res.net, None)
     del vp, x, y
     rows = Cr.evaluate(w, res.net, *ev, log=_log)
     summ = Cr.summarize(rows)
     lbm.lbm_nn_destroy(res.net)
-    out = {
+    ch = w.channels
+    flops = sum(2 * 27 * ch[l] * ch[l + 1] for l in range(len(ch) - 1)) * V
+    extras = dict(w=w, tr=tr, ev=ev, n_pairs=n_pairs, t_data=t_data, val_loss=val_loss, zero_loss=zero_loss,
+                  fwd_s=fwd_s, flops=flops)
+    return rows, summ, res, extras
+
+
+def learned_record(rows, summ, res, x, epochs):
+    """The learned-corrector figures as a JSON object."""
+    w = x["w"]
+    return {
         "metric": "kinetic-energy spectrum error at equal wall time, learned vs plain (D3Q27 64^3)",
-        "value": round(summ["learned"], 5),
         "unit": "RMS of log(E/E_ref) over shells 1-32",
+        "learned_error": round(summ["learned"], 5),
+        "plain_equal_time_error": round(summ["plain_equal_time"], 5),
+        "plain_coarse_error": round(summ["plain_coarse"], 5),
+        "equal_time_grids": summ["equal_time_grids"],
+        "wins_equal_time": f"{summ['wins_equal_time']}/{summ['seeds']}",
+        "seeds_plain_coarse_unstable": summ["seeds_plain_coarse_unstable"],
+        "config": {"workload": "learned corrector: D3Q27 decaying turbulence 64^3 FP32 + 4-layer 3x3x3 conv "
+                               "(32 ch, bf16 matrix cores; reads rho, u, T, corrects u), trained on 256^3 runs "
+                               "box-filtered 4^3 -> 64^3",
+                   "training_seeds": len(x["tr"][0]), "evaluation_seeds": x["ev"][0], "Ma_t_eval": x["ev"][1],
+                   "epochs": epochs, "correction_every_coarse_steps": w.every, "coarse_steps": w.coarse_steps,
+                   "fine_steps": w.coarse_steps * w.factor},
+        "per_seed": [{"seed": r["seed"], "Ma_t": round(r["Ma_t"], 4),
+                      "learned": [round(r["learned"]["error"], 5), round(1e3 * r["learned"]["seconds"], 2)],
+                      "plain": [[p["n"], round(p["error"], 5), round(1e3 * p["seconds"], 2)] for p in r["plain"]]}
+                     for r in rows],
+        "training": {"pairs": x["n_pairs"], "seeds_used": x["n_pairs"] // w.windows,
+                     "data_seconds": round(x["t_data"], 1), "train_seconds": round(res.seconds, 1),
+                     "loss_first_epoch": round(res.history[0], 5), "loss_last_epoch": round(res.history[-1], 5),
+                     "validation_loss": round(x["val_loss"], 5), "no_correction_loss": round(x["zero_loss"], 5)},
+        "network_forward": {"avg_ms": round(x["fwd_s"] * 1e3, 4),
+                            "TFLOPs": round(x["flops"] / x["fwd_s"] / 1e12, 2),
+                            "frac_of_bf16_peak": round(x["flops"] / x["fwd_s"] / 1e12 / 2500.0, 5)},
+    }
+
+
+def run_learned(args, torch, lbm, dev):
+    """The learned workload (see the module docstring)."""
+    rows, summ, res, x = learned_evaluation(torch, lbm, dev, args.steps, args.train_seeds, args.eval_seeds, args.lr)
+    rec = learned_record(rows, summ, res, x, args.steps)
+    tflops = x["flops"] / x["fwd_s"] / 1e12
+    out = {
+        "metric": rec["metric"],
+        "value": rec["learned_error"],
+        "unit": rec["unit"],
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": 0,
@@ -266,31 +314,21 @@ def run_learned(args, torch, lbm, dev):
         "vs_baseline": None,
         "dtype": "f32 populations, bf16 network (fp32 accumulation)",
         "data": "synthetic (seeded, no dataset); reference = the method's own 256^3 runs, box-filtered",
-        "config": {"workload": "learned corrector: D3Q27 decaying turbulence 64^3 FP32 + 4-layer 3x3x3 conv "
-                               "(32 ch; reads rho, u, T, corrects u), trained on 256^3 runs box-filtered 4^3 -> 64^3",
-                   "training_seeds": len(tr[0]), "evaluation_seeds": ev[0], "Ma_t_eval": ev[1],
-                   "correction_every_coarse_steps": w.every, "coarse_steps": w.coarse_steps,
-                   "fine_steps": w.coarse_steps * w.factor, "epochs": args.steps, "parallelism": "single GPU"},
-        "plain_coarse_error": round(summ["plain_coarse"], 5),
-        "plain_equal_time_error": round(summ["plain_equal_time"], 5),
-        "equal_time_grids": summ["equal_time_grids"],
-        "wins_equal_time": f"{summ['wins_equal_time']}/{summ['seeds']}",
-        "seeds_plain_coarse_unstable": summ["seeds_plain_coarse_unstable"],
-        "per_seed": [{"seed": r["seed"], "Ma_t": round(r["Ma_t"], 4),
-                      "learned": [round(r["learned"]["error"], 5), round(1e3 * r["learned"]["seconds"], 2)],
-                      "plain": [[p["n"], round(p["error"], 5), round(1e3 * p["seconds"], 2)] for p in r["plain"]]}
-                     for r in rows],
-        "training": {"pairs": n_pairs, "seeds_used": n_pairs // w.windows, "data_seconds": round(t_data, 1),
-                     "train_seconds": round(res.seconds, 1), "loss_first_epoch": round(res.history[0], 5),
-                     "loss_last_epoch": round(res.history[-1], 5), "validation_loss": round(val_loss, 5),
-                     "no_correction_loss": round(zero_loss, 5)},
+        "config": dict(rec["config"], parallelism="single GPU"),
+        "plain_coarse_error": rec["plain_coarse_error"],
+        "plain_equal_time_error": rec["plain_equal_time_error"],
+        "equal_time_grids": rec["equal_time_grids"],
+        "wins_equal_time": rec["wins_equal_time"],
+        "seeds_plain_coarse_unstable": rec["seeds_plain_coarse_unstable"],
+        "per_seed": rec["per_seed"],
+        "training": rec["training"],
         "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": round(tflops / 2500.0, 5), "traffic": None,
                      "kernel": "network forward at 64^3 (4 conv launches + input packing)",
-                     "avg_forward_ms": round(fwd_s * 1e3, 4), "algorithmic_flops_per_forward": flops},
+                     "avg_forward_ms": round(x["fwd_s"] * 1e3, 4), "algorithmic_flops_per_forward": x["flops"]},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_forward_baseline(w)
+        out["cpu_baseline"] = cpu_forward_baseline(x["w"])
     return out
 
 
@@ -371,9 +409,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", choices=["turbulence3d", "shockvortex2d", "ensemble2d", "learned64", "nnforward64"],
                     default="turbulence3d")
-    ap.add_argument("--train-seeds", type=int, default=32, help="learned64: training seeds")
-    ap.add_argument("--eval-seeds", type=int, default=4, help="learned64: held-out seeds")
-    ap.add_argument("--lr", type=float, default=1e-3, help="learned64: Adam learning rate")
+    ap.add_argument("--train-seeds", type=int, default=32, help="learned corrector: training seeds")
+    ap.add_argument("--eval-seeds", type=int, default=4, help="learned corrector: held-out seeds")
+    ap.add_argument("--lr", type=float, default=1e-3, help="learned corrector: Adam learning rate")
     ap.add_argument("--graph-steps", type=int, default=50, help="ensemble2d: steps per captured HIP graph")
     ap.add_argument("--n", type=int, default=0, help="box edge (default 256 for turbulence3d, 1024 for shockvortex2d)")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
@@ -384,6 +422,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=2048, help="size of the copy-kernel reference")
+    ap.add_argument("--pattern-launches", type=int, default=20,
+                    help="launches of the step kernel's access-pattern reference (0: skip)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="turbulence3d: skip the learned-corrector evaluation appended to the JSON line")
+    ap.add_argument("--learned-epochs", type=int, default=100,
+                    help="turbulence3d: training epochs of the appended learned-corrector evaluation")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -450,6 +494,17 @@ def main():
     d = lbm.lbm_diagnostics(h)
     if d["nonfinite"] or d["nonpositive"]:
         _log("[bench] WARNING: the state has non-finite or non-positive values")
+    # the step kernel's access pattern alone (same loads and stores, no collision), same tile and stream
+    pattern_ms = None
+    if args.pattern_launches:
+        lbm.lbm_pattern_reference(h, 2)
+        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        p0.record(stream)
+        lbm.lbm_pattern_reference(h, args.pattern_launches)
+        p1.record(stream)
+        torch.cuda.synchronize()
+        pattern_ms = p0.elapsed_time(p1) / args.pattern_launches
+        _log(f"[bench] access-pattern reference {pattern_ms:.3f} ms per launch")
     lbm.lbm_destroy(h)
 
     # reference: the library's own copy kernel over a large buffer
@@ -497,6 +552,13 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "kernel": "step_kernel", "avg_kernel_ms": round(avg_kernel_s * 1e3, 4),
                      "algorithmic_bytes_per_launch": bytes_per_node * N},
+        "pattern_reference": None if pattern_ms is None else {
+            "kernel": "pattern_kernel (the step kernel's loads, stores, LDS exchange and barriers; no collision)",
+            "avg_kernel_ms": round(pattern_ms, 4),
+            "achieved": round(bytes_per_node * N / (pattern_ms / 1e3) / 1e9, 1),
+            "frac": round(bytes_per_node * N / (pattern_ms / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "unit": "GB/s",
+            "step_fraction_of_pattern": round(pattern_ms / (avg_kernel_s * 1e3), 4)},
         "copy_kernel_GBps": round(copy_gbps, 1) if copy_gbps else None,
         "hbm_fraction_of_copy": round(achieved / copy_gbps, 4) if copy_gbps else None,
         "kernel_source": kernel_source_hash(),
@@ -507,6 +569,14 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
         out["cpu_baseline"]["gpu_speedup"] = round(mlups / out["cpu_baseline"]["value"], 1)
+    if args.workload == "turbulence3d" and n == 256 and not args.no_learned:
+        # the second half of the benchmark's metric: the learned corrector
+        # against the plain method at equal wall time (fixed epoch count)
+        _log(f"[bench] learned corrector: {args.learned_epochs} epochs, {args.train_seeds} training seeds, "
+             f"{args.eval_seeds} held-out seeds")
+        rows, summ, res, x = learned_evaluation(torch, lbm, dev, args.learned_epochs, args.train_seeds,
+                                                args.eval_seeds, args.lr)
+        out["learned_corrector"] = learned_record(rows, summ, res, x, args.learned_epochs)
     print(json.dumps(out), flush=True)
 
 

@@ -189,6 +189,20 @@ int lbm_fields_set(lbm_handle h, const double* rho, const double* u, const doubl
    mass, momentum and energy are kept.  Outputs on the coarse grid (node
    order as for the fields). */
 int lbm_filter_moments(lbm_handle h, int factor, double* rho, double* u, double* T, int mem);
+/* Measurement kernel: the memory-access pattern of one lbm_step alone.
+   Each of launches launches runs, with the handle's launch tile, a kernel
+   that loads exactly what a step loads (the pull sources of every node, of
+   the one-node halo ring and of the planes next to each march chunk),
+   exchanges the same values through LDS with the same barriers and stores
+   exactly what a step stores, but does no collision: it writes the streamed
+   populations, plus about one addition per loaded value so that no load is
+   dead.  It reads the current populations and writes the other buffer, so
+   the state and the step count are unchanged.  Asynchronous on the handle's
+   stream.  Its bytes per node are those of a step, so its time is the
+   ceiling a step kernel with this access pattern can reach.  LBM_EINVAL on
+   a NULL handle, launches < 0 or a handle with cv_poly; LBM_ESTATE before
+   lbm_init_fields. */
+int lbm_pattern_reference(lbm_handle h, int64_t launches);
 /* Plain device-to-device copy of bytes (multiple of 16) on hip_stream, by the
    library's own vectorised copy kernel: the reference for achievable HBM
    bandwidth and for scaling hardware byte counters. */

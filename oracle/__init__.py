@@ -75,6 +75,7 @@ def lib():
         L.orc_step_sampled_branch.argtypes = [C.c_void_p, C.POINTER(C.c_long), C.c_long, C.POINTER(C.c_byte),
                                               _dp, _dp]
         L.orc_set_fp32_storage.argtypes = [C.c_void_p, _dp, _dp]
+        L.orc_set_upwind_band.argtypes = [C.c_void_p, C.c_double]
         L.orc_step_count.restype = C.c_long
         L.orc_step_count.argtypes = [C.c_void_p]
         L.orc_moments.argtypes = [C.c_void_p, _dp, _dp, _dp]
@@ -303,6 +304,11 @@ class Sim:
         assert fr.size == Q(self.D) and gr.size == Q(self.D)
         if lib().orc_set_fp32_storage(self._h, _ptr(fr), _ptr(gr)) != 0:
             raise ValueError("oracle: non-finite storage reference")
+
+    def set_upwind_band(self, band):
+        """Upwind-side ambiguity model (see oracle.h); 0 switches it off."""
+        if lib().orc_set_upwind_band(self._h, float(band)) != 0:
+            raise ValueError("oracle: bad upwind band")
 
     def moments(self):
         rho = np.zeros(self.shape)

@@ -64,6 +64,8 @@ struct orc_sim {
      deviations are rounded to single precision after init and every step */
   int fp32_store;
   double fref[QMAX], gref[QMAX];
+  /* upwind decisions with |u| <= band take the other side (orc_set_upwind_band) */
+  double band;
 };
 
 static void round_storage(orc_sim* s);
@@ -488,7 +490,9 @@ void orc_derivative(const orc_sim* s, int axis, const double* Qt, const double* 
       out[n] = 0.5 * (Qt[np] - Qt[nm]);
     } else {
       double q_plus, q_minus;
-      if (u[n] > 0.0) {
+      int backward = u[n] > 0.0;
+      if (s->band > 0.0 && fabs(u[n]) <= s->band) backward = !backward;
+      if (backward) {
         q_plus = Qt[n];
         q_minus = Qt[nm];
       } else {
@@ -570,6 +574,12 @@ static void round_storage(orc_sim* s) {
       *f = s->fref[i] + (double)(float)(*f - s->fref[i]);
       *g = s->gref[i] + (double)(float)(*g - s->gref[i]);
     }
+}
+
+int orc_set_upwind_band(orc_sim* s, double band) {
+  if (!(band >= 0.0) || !isfinite(band)) return -1;
+  s->band = band;
+  return 0;
 }
 
 int orc_set_fp32_storage(orc_sim* s, const double* f_ref, const double* g_ref) {

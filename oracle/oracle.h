@@ -96,6 +96,13 @@ int orc_step_sampled_branch(const orc_sim* s, const long* nodes, long count, con
    FP32 deviation storage alone costs a flow.  NULL pointers switch it off.
    Returns -1 on a non-finite reference value. */
 int orc_set_fp32_storage(orc_sim* s, const double* f_ref, const double* g_ref);
+/* Upwind-side ambiguity model: from now on every upwind decision of
+   Sec. III.A whose |u_a| <= band takes the other side than the sign test
+   (where a perturbation of u of that size could change the side, both are
+   valid readings).  band = 0 (default) is the plain scheme, u_a = 0
+   included.  Returns -1 on a
+   negative or non-finite band. */
+int orc_set_upwind_band(orc_sim* s, double band);
 long orc_step_count(const orc_sim* s);
 /* Moments of the stored populations (no streaming). */
 int orc_moments(const orc_sim* s, double* rho, double* u, double* T);

@@ -16,7 +16,11 @@ namespace lbm {
 struct StepParams {
   int nx, ny, nz;
   int bc[3];            // LBM_BC_* per axis
-  long long ps;         // elements between the arrays of two consecutive populations of one plane
+  // Layout of one march plane: in-plane node q sits in 64-node block q / 64
+  // at lane q % 64; element (f or g) s of slot i is at
+  //   (q / 64) * blk + i * sl + 2 (q % 64) + s.
+  long long sl;         // elements between the same block of two consecutive slots
+  long long blk;        // elements between two consecutive 64-node blocks of one slot
   long long ms;         // elements between two consecutive march planes (z for D3Q27, y for D2Q9)
   int plane;            // nodes per march plane (nx*ny for D3Q27, nx for D2Q9)
   int tiles_x, tiles_y; // in-plane tiles (tiles_y == 1 for D2Q9)
@@ -57,7 +61,8 @@ struct Ctx {
   int precision = 0;
   int64_t n[3] = {1, 1, 1};
   int64_t N = 0;
-  long long ps = 0;       // population stride inside a plane
+  long long sl = 0;       // slot stride inside a plane (see StepParams)
+  long long blk = 0;      // 64-node block stride inside a plane
   long long ms = 0;       // march-plane stride
   int nm = 0;             // number of march planes
   int device = 0;
@@ -106,6 +111,8 @@ struct Batch {
 
 // ---- launchers (lbm_kernels.hip) -------------------------------------------
 hipError_t launch_step(const Ctx& c, const void* src, void* dst);
+// The step kernel's access pattern without the node arithmetic (measurement).
+hipError_t launch_pattern(const Ctx& c, const void* src, void* dst);
 hipError_t launch_init(const Ctx& c, const double* rho, const double* u, const double* T, void* dst);
 hipError_t launch_fields(const Ctx& c, const void* pops, double* fields);
 hipError_t launch_diag(const Ctx& c, const double* fields, double* partial, int nblocks, double* out);

@@ -64,8 +64,16 @@ __device__ inline int fix_near(int k, int n, int bc) {
 // node n (node = x + nx*(y + ny*z)).
 __device__ inline long long pop_offset(const StepParams& p, int Q, int i, long long n) {
   const long long m = n / p.plane;
+  const long long q = n - m * p.plane;
   const int slot = i < Q ? i : i - Q;
-  return m * p.ms + (long long)slot * 2 * p.ps + 2 * (n - m * p.plane) + (i < Q ? 0 : 1);
+  return m * p.ms + (q >> 6) * p.blk + (long long)slot * p.sl + 2 * (q & 63) + (i < Q ? 0 : 1);
+}
+
+// Byte offset of the (f, g) pair of slot 0 of in-plane node q within its
+// march plane.
+template <typename S>
+__device__ inline unsigned inplane_bytes(const StepParams& p, int q) {
+  return (unsigned)(((unsigned long long)(q >> 6) * (unsigned long long)p.blk + 2u * (unsigned)(q & 63)) * sizeof(S));
 }
 
 template <typename S>
@@ -204,11 +212,56 @@ __device__ inline NodeMoments<R> pulled_moments_batched(const __amdgpu_buffer_rs
   return m;
 }
 
+// Stand-ins for the node arithmetic in the access-pattern reference kernel
+// (PAT): each keeps the values it is given live at the cost of about one
+// addition per value, so that the kernel loads and stores exactly what a
+// step does and computes nothing else.
+template <int D, typename R>
+__device__ inline NodeMoments<R> pattern_moments(const R* f, const R* g) {
+  NodeMoments<R> m{};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) m.u[a] = f[a] + g[a];
+  return m;
+}
+
+// All 2Q values (the halo node and the plane before a chunk, where a step
+// forms the conserved sums).
+template <int D, typename R>
+__device__ inline NodeMoments<R> pattern_all(const R* f, const R* g) {
+  constexpr int Q = lat_q(D);
+  R acc = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) acc += f[i] + g[i];
+  NodeMoments<R> m{};
+  m.u[0] = m.u[1] = m.u[2] = acc;
+  return m;
+}
+
+template <int D, typename S, typename R>
+__device__ inline NodeMoments<R> pattern_pulled(const __amdgpu_buffer_rsrc_t* rs, unsigned slot_bytes,
+                                                const unsigned* lo) {
+  constexpr int Q = lat_q(D);
+  R acc = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int cx = vx(i);
+    const int cy = (D == 3) ? vy(i) : 0;
+    const int cm = (D == 3) ? vz(i) : vy(i);
+    const auto v = Buf<S>::load(rs[1 - cm], lo[(1 - cy) * 3 + (1 - cx)], (unsigned)i * slot_bytes);
+    acc += (R)v.x + (R)v.y;
+  }
+  NodeMoments<R> m{};
+  m.u[0] = m.u[1] = m.u[2] = acc;
+  return m;
+}
+
 // One work-group's share of a step: tile lb (x fastest, then y, then the
 // march chunk) of the box described by p.  CAL: the general caloric law
 // (p.caloric must equal CAL); with CAL false the constant-C_v arithmetic is
 // all the kernel contains.
-template <int D, bool DEV, typename S, int BX, int BY, bool CAL = false>
+// PAT: the access-pattern reference (same loads, stores, LDS exchange and
+// barriers, no collision: the streamed populations are stored).
+template <int D, bool DEV, typename S, int BX, int BY, bool CAL = false, bool PAT = false>
 __device__ inline void step_tile(const S* __restrict__ src, S* __restrict__ dst, const StepParams& p, int lb) {
   using R = typename StoreOf<S>::R;
   constexpr int Q = lat_q(D);
@@ -232,7 +285,6 @@ __device__ inline void step_tile(const S* __restrict__ src, S* __restrict__ dst,
   const int nm = (D == 3) ? p.nz : p.ny;
   const int bc0 = p.bc[0], bc1 = p.bc[1], bcm = (D == 3) ? p.bc[2] : p.bc[1];
   const long long sm = p.ms;  // march-plane stride
-  const long long ps = p.ps;
 
   const int t = threadIdx.x;
   const int lx = t % BX, ly = t / BX;
@@ -284,46 +336,66 @@ __device__ inline void step_tile(const S* __restrict__ src, S* __restrict__ dst,
   // header), in up to 512 registers at one wavefront per SIMD.  FP64 needs
   // twice the registers per population, and 512-thread groups have half the
   // registers per thread: one plane in flight.
-  constexpr bool PF2 = DEV && BX * BY <= 256;
-  const unsigned slot_bytes = (unsigned)(2 * ps * (long long)sizeof(S));
+  // The pattern reference holds no arithmetic state, so it keeps two planes
+  // in flight for every shape: the best latency hiding the access pattern
+  // allows.
+  constexpr bool PF2 = PAT || (DEV && BX * BY <= 256);
+  const unsigned slot_bytes = (unsigned)(p.sl * (long long)sizeof(S));
   const long long plane_bytes = sm * (long long)sizeof(S);
   // byte offsets of the 9 in-plane sources of the core and of the halo node
   unsigned clo[9], hlo[9];
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
-    clo[j] = (unsigned)(2 * sizeof(S) * (unsigned)(coy[j / 3] + cox[j % 3]));
-    hlo[j] = (unsigned)(2 * sizeof(S) * (unsigned)(hoy[j / 3] + hox[j % 3]));
+    clo[j] = inplane_bytes<S>(p, coy[j / 3] + cox[j % 3]);
+    hlo[j] = inplane_bytes<S>(p, hoy[j / 3] + hox[j % 3]);
   }
   auto march_planes = [&](int m, __amdgpu_buffer_rsrc_t* rs) {
     const int mn = fix_near(m, nm, bcm);  // m0 - 1 <= m <= m1 + 1
 #pragma unroll
     for (int j = 0; j < 3; ++j) rs[j] = plane_rsrc(src + (long long)fix_near(mn + j - 1, nm, bcm) * sm, plane_bytes);
   };
+  // Node arithmetic (or its stand-ins in the pattern reference).
+  auto anom = [&](const NodeMoments<R>& mm, int a) -> R {
+    if constexpr (PAT) return mm.u[a];
+    else return anomaly(mm, a, k);
+  };
+  auto moments = [&](const R* f, const R* g) -> NodeMoments<R> {
+    if constexpr (PAT) return pattern_moments<D, R>(f, g);
+    else return node_moments<D, R>(f, g, k);
+  };
+  auto moments_light = [&](const R* f, const R* g) -> NodeMoments<R> {
+    if constexpr (PAT) return pattern_all<D, R>(f, g);
+    else if constexpr (DEV) return node_moments_light<D>(f, g, k);
+    else return node_moments<D, R>(f, g, k);
+  };
   // The halo node's anomaly into LDS buffer buf.
   auto halo_store = [&](const NodeMoments<R>& mm, int buf) {
     if (D == 3) {
-      if (hslot == 0) lq1[buf][0][t] = anomaly(mm, 1, k);
-      else if (hslot == 1) lq1[buf][BY + 1][t - BX] = anomaly(mm, 1, k);
-      else if (hslot == 2) lq0[buf][t - 2 * BX][0] = anomaly(mm, 0, k);
-      else lq0[buf][t - 2 * BX - BY][BX + 1] = anomaly(mm, 0, k);
+      if (hslot == 0) lq1[buf][0][t] = anom(mm, 1);
+      else if (hslot == 1) lq1[buf][BY + 1][t - BX] = anom(mm, 1);
+      else if (hslot == 2) lq0[buf][t - 2 * BX][0] = anom(mm, 0);
+      else lq0[buf][t - 2 * BX - BY][BX + 1] = anom(mm, 0);
     } else {
-      lq0[buf][0][hslot == 2 ? 0 : BX + 1] = anomaly(mm, 0, k);
+      lq0[buf][0][hslot == 2 ? 0 : BX + 1] = anom(mm, 0);
     }
   };
   // ... from populations already in registers (FP32 only) ...
   auto halo_finish = [&](const R* f, const R* g, int buf) {
-    if constexpr (DEV) {
-      if (has_halo) halo_store(node_moments_light<D>(f, g, k), buf);
+    if constexpr (DEV || PAT) {
+      if (has_halo) halo_store(moments_light(f, g), buf);
     }
   };
   // ... or loaded now, in batches.
   auto halo_direct = [&](const __amdgpu_buffer_rsrc_t* rs, int buf) {
-    if (has_halo) halo_store(pulled_moments_batched<D, S, R>(rs, slot_bytes, hlo, k), buf);
+    if (has_halo) {
+      if constexpr (PAT) halo_store(pattern_pulled<D, S, R>(rs, slot_bytes, hlo), buf);
+      else halo_store(pulled_moments_batched<D, S, R>(rs, slot_bytes, hlo, k), buf);
+    }
   };
   // Own node's in-plane anomalies into LDS buffer buf.
   auto core_publish = [&](const NodeMoments<R>& mm, int buf) {
-    lq0[buf][ly][lx + 1] = anomaly(mm, 0, k);
-    if (D == 3) lq1[buf][ly + 1][lx] = anomaly(mm, 1, k);
+    lq0[buf][ly][lx + 1] = anom(mm, 0);
+    if (D == 3) lq1[buf][ly + 1][lx] = anom(mm, 1);
   };
 
   R qm_prev, qm_cur, qm_next;  // anomaly along the march axis at m - 1, m, m + 1
@@ -335,18 +407,16 @@ __device__ inline void step_tile(const S* __restrict__ src, S* __restrict__ dst,
     __amdgpu_buffer_rsrc_t rs[3];
     march_planes(m0 - 1, rs);
     pull<D, S, R>(rs, slot_bytes, clo, f0, g0);
-    NodeMoments<R> mm;
-    if constexpr (DEV) mm = node_moments_light<D>(f0, g0, k);
-    else mm = node_moments<D, R>(f0, g0, k);
-    qm_prev = anomaly(mm, D - 1, k);
+    const NodeMoments<R> mm = moments_light(f0, g0);
+    qm_prev = anom(mm, D - 1);
   }
   // plane m0: core populations stay in registers, in-plane anomaly to LDS
   {
     __amdgpu_buffer_rsrc_t rs[3];
     march_planes(m0, rs);
     pull<D, S, R>(rs, slot_bytes, clo, f0, g0);
-    mo0 = node_moments<D, R>(f0, g0, k);
-    qm_cur = anomaly(mo0, D - 1, k);
+    mo0 = moments(f0, g0);
+    qm_cur = anom(mo0, D - 1);
     core_publish(mo0, 0);
     halo_direct(rs, 0);
   }
@@ -368,8 +438,8 @@ __device__ inline void step_tile(const S* __restrict__ src, S* __restrict__ dst,
       __amdgpu_buffer_rsrc_t rs[3];
       march_planes(more ? m + 2 : m + 1, rs);
       if (more) pull<D, S, R>(rs, slot_bytes, clo, fc, gc);
-      mb = node_moments<D, R>(fb, gb, k);
-      qm_next = anomaly(mb, D - 1, k);
+      mb = moments(fb, gb);
+      qm_next = anom(mb, D - 1);
       core_publish(mb, nb);
       halo_finish(hf, hg, nb);
       if (more && has_halo) pull<D, S, R>(rs, slot_bytes, hlo, hf, hg);
@@ -379,8 +449,8 @@ __device__ inline void step_tile(const S* __restrict__ src, S* __restrict__ dst,
       __amdgpu_buffer_rsrc_t rs[3];
       march_planes(m + 1, rs);
       pull<D, S, R>(rs, slot_bytes, clo, fb, gb);
-      mb = node_moments<D, R>(fb, gb, k);
-      qm_next = anomaly(mb, D - 1, k);
+      mb = moments(fb, gb);
+      qm_next = anom(mb, D - 1);
       core_publish(mb, nb);
       halo_direct(rs, nb);
     }
@@ -394,10 +464,11 @@ __device__ inline void step_tile(const S* __restrict__ src, S* __restrict__ dst,
       dd[1] = anomaly_derivative<R>(p.deriv, ma.u[1], qm_prev, qm_cur, qm_next);
       dd[2] = (R)0;
     }
-    collide<D, R, DEV>(fa, ga, ma, dd, k);
+    if constexpr (PAT) fa[0] += (dd[0] + dd[1]) + dd[2];
+    else collide<D, R, DEV>(fa, ga, ma, dd, k);
     if (active) {
       const __amdgpu_buffer_rsrc_t rd = plane_rsrc(dst + (long long)m * sm, plane_bytes);
-      const unsigned o = (unsigned)(2 * sizeof(S) * (unsigned)cnode);
+      const unsigned o = inplane_bytes<S>(p, cnode);
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         typename Buf<S>::pair_t v;
@@ -445,6 +516,13 @@ template <int D, bool DEV, typename S, int BX, int BY, bool CAL = false>
 __global__ void __launch_bounds__(BX* BY) step_kernel(const S* __restrict__ src, S* __restrict__ dst,
                                                       const StepParams p) {
   step_tile<D, DEV, S, BX, BY, CAL>(src, dst, p, xcd_logical_block(blockIdx.x, p.nblocks));
+}
+
+// The access-pattern reference of step_kernel (see step_tile).
+template <int D, bool DEV, typename S, int BX, int BY>
+__global__ void __launch_bounds__(BX* BY) pattern_kernel(const S* __restrict__ src, S* __restrict__ dst,
+                                                         const StepParams p) {
+  step_tile<D, DEV, S, BX, BY, false, true>(src, dst, p, xcd_logical_block(blockIdx.x, p.nblocks));
 }
 
 // Several boxes in one launch: logical block g belongs to the last box whose
@@ -745,7 +823,9 @@ int default_chunk(int D, const int64_t n[3], int bx, int by) {
   return (int)(chunk < n[1] ? chunk : n[1]);
 }
 
-// Default launch shape and march chunk.  D3Q27: the compiled shape with the
+// Default launch shape and march chunk (32 x 16 tiles, the 512-thread shape
+// with the smallest halo ring, measured 10% slower than 64 x 8 at 256^3 FP32
+// and are not compiled).  D3Q27: the compiled shape with the
 // lowest march_cost at its best chunk — 64 x 4, 32 x 8 and, for FP32
 // storage, 64 x 8 (the only 512-thread shape that fits 256 registers
 // without spilling); the caloric variant is compiled for 64 x 4 only.  On
@@ -809,6 +889,38 @@ static hipError_t dispatch_tile(const Ctx& c, const void* src, void* dst) {
     if (t.bx == 256) return launch_step_t<D, DEV, S, 256, 1>(c, src, dst);
   }
   return hipErrorInvalidValue;
+}
+
+template <int D, bool DEV, typename S, int BX, int BY>
+static hipError_t launch_pattern_t(const Ctx& c, const void* src, void* dst) {
+  hipLaunchKernelGGL((pattern_kernel<D, DEV, S, BX, BY>), dim3(c.sp.nblocks), dim3(BX * BY), 0, c.stream,
+                     static_cast<const S*>(src), static_cast<S*>(dst), c.sp);
+  return hipGetLastError();
+}
+
+template <int D, bool DEV, typename S>
+static hipError_t dispatch_pattern(const Ctx& c, const void* src, void* dst) {
+  const Tile& t = c.tile;
+  if constexpr (D == 3) {
+    if (t.bx == 64 && t.by == 4) return launch_pattern_t<D, DEV, S, 64, 4>(c, src, dst);
+    if constexpr (DEV)
+      if (t.bx == 64 && t.by == 8) return launch_pattern_t<D, DEV, S, 64, 8>(c, src, dst);
+    if (t.bx == 32 && t.by == 8) return launch_pattern_t<D, DEV, S, 32, 8>(c, src, dst);
+  } else {
+    if (t.bx == 64) return launch_pattern_t<D, DEV, S, 64, 1>(c, src, dst);
+    if (t.bx == 128) return launch_pattern_t<D, DEV, S, 128, 1>(c, src, dst);
+    if (t.bx == 256) return launch_pattern_t<D, DEV, S, 256, 1>(c, src, dst);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_pattern(const Ctx& c, const void* src, void* dst) {
+  if (c.lattice == 3) {
+    if (c.precision == LBM_FP64) return dispatch_pattern<3, false, double>(c, src, dst);
+    return dispatch_pattern<3, true, float>(c, src, dst);
+  }
+  if (c.precision == LBM_FP64) return dispatch_pattern<2, false, double>(c, src, dst);
+  return dispatch_pattern<2, true, float>(c, src, dst);
 }
 
 hipError_t launch_step(const Ctx& c, const void* src, void* dst) {

@@ -109,12 +109,13 @@ def _load():
     L.lbm_batch_get_tile.argtypes = [vp, C.POINTER(C.c_int)]
     L.lbm_get_tile.argtypes = [vp, C.POINTER(C.c_int)]
     L.lbm_get_dims.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(i64)]
+    L.lbm_pattern_reference.argtypes = [vp, i64]
     L.lbm_batch_tune.argtypes = [vp, C.c_int, dp]
     L.lbm_batch_step.argtypes = [vp, i64, C.c_int]
     for name in ("lbm_create", "lbm_destroy", "lbm_set_stream", "lbm_init_fields", "lbm_step", "lbm_moments",
                  "lbm_diagnostics", "lbm_get_state", "lbm_set_state", "lbm_device_copy", "lbm_batch_create",
                  "lbm_batch_destroy", "lbm_batch_set_stream", "lbm_batch_set_tile", "lbm_batch_get_tile",
-                 "lbm_get_tile", "lbm_get_dims", "lbm_batch_tune", "lbm_batch_step", "lbm_fields_add", "lbm_filter_moments", "lbm_nn_create",
+                 "lbm_get_tile", "lbm_get_dims", "lbm_pattern_reference", "lbm_batch_tune", "lbm_batch_step", "lbm_fields_add", "lbm_filter_moments", "lbm_nn_create",
                  "lbm_nn_destroy", "lbm_nn_set_stream", "lbm_nn_set_params", "lbm_nn_get_params", "lbm_nn_get_grads",
                  "lbm_nn_zero_grad", "lbm_nn_set_scaling", "lbm_nn_forward", "lbm_nn_loss_backward",
                  "lbm_nn_adam_step", "lbm_nn_take_loss", "lbm_nn_correct", "lbm_nn_fields_to_planes", "lbm_fields_set",
@@ -267,6 +268,10 @@ def lbm_init_fields(h, rho, u, T) -> int:
 
 def lbm_step(h, n: int = 1) -> int:
     return _check(_L.lbm_step(h, int(n)))
+
+
+def lbm_pattern_reference(h, launches: int = 1) -> int:
+    return _check(_L.lbm_pattern_reference(h, int(launches)))
 
 
 def lbm_moments(h, rho=None, u=None, T=None):

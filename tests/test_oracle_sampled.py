@@ -159,3 +159,33 @@ def test_fp32_storage_model_rounds_only_the_deviation():
     exact.step(1)
     rounded.step(1)
     assert np.array_equal(exact.get_pops()[0], rounded.get_pops()[0])
+
+
+def test_upwind_band_reverses_only_the_decisions_within_the_band():
+    """orc_set_upwind_band: every upwind decision of Sec. III.A with
+    |u_a| <= band takes the other side; the others, and every decision with
+    band 0 (u_a = 0 included: the 'otherwise' side), are the plain scheme's."""
+    dims = (12, 3, 2)
+    s = oracle.Sim(3, dims, gamma=1.4, Pr=0.7, mu=0.02)
+    x = np.arange(12, dtype=float)
+    Qt = np.broadcast_to(x ** 2 + 0.5 * x ** 3, (2, 3, 12)).copy()
+    uv = np.array([0.3, 1e-9, -1e-9, 0.0, -0.2, 5e-9, 2e-8, -2e-8, 1e-8, -1e-8, 0.1, -0.1])
+    u = np.broadcast_to(uv, (2, 3, 12)).copy()
+    q = Qt[0, 0]
+
+    def expected(band):
+        out = np.zeros(12)
+        for k in range(12):
+            backward = uv[k] > 0
+            if band > 0 and abs(uv[k]) <= band:
+                backward = not backward
+            out[k] = q[k] - q[k - 1] if backward else q[(k + 1) % 12] - q[k]
+        return out
+
+    for band in (0.0, 1e-8, 3e-9):
+        s.set_upwind_band(band)
+        d = s.derivative(0, Qt, u)
+        assert np.array_equal(d[0, 0], expected(band)), band
+    assert not np.array_equal(expected(1e-8), expected(0.0))
+    with pytest.raises(ValueError):
+        s.set_upwind_band(-1.0)
