@@ -156,6 +156,23 @@ int lbm_moments(lbm_handle h, double* rho, double* u, double* T, int mem);
    on first use.  LBM_EINVAL on a NULL argument, LBM_ESTATE before
    lbm_init_fields. */
 int lbm_diagnostics(lbm_handle h, lbm_diag* out);
+/* lbm_diagnostics for callers that cannot allocate device memory (code
+   under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc): the same sums into *out (host), formed straight from the
+   stored populations by the same arithmetic over the same grid, with no
+   field buffer and no allocation.  The block partial sums and the final
+   sums live in a library-owned device array of 2048 x 21 + 21 doubles
+   (344 KB) on each device, obtained at lbm_create and held until the
+   process ends; it covers any grid lbm_create accepts (at most 2048
+   partial sums), and a reduction that would need more is refused with
+   LBM_EINVAL.  All calls on one device share that array and each call
+   overwrites it: calls that overlap on one device (from several host
+   threads, or on several streams of the device) race and must be serialised
+   by the caller.  Synchronous on the handle's stream.  Sets the instability
+   flag as lbm_diagnostics does.  LBM_EINVAL on a NULL argument, LBM_ESTATE
+   before lbm_init_fields, LBM_EDEVICE if a HIP call (or the scratch
+   address) fails. */
+int lbm_diagnostics_noalloc(lbm_handle h, lbm_diag* out);
 /* Raw state for checkpoints: 2Q population planes of N values (f then g) in
    the storage type (FP64: double values; FP32_DEV: float deviations). */
 size_t lbm_state_bytes(lbm_handle h);

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -154,6 +155,52 @@ bool fields_valid_host(const double* rho, const double* u, const double* T, int6
   return true;
 }
 
+// The device address of the allocation-free diagnostics' scratch array on
+// each device, obtained once per device with that device current.
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+double* g_scratch[kMaxDevices] = {};
+
+int scratch_for_device(int device, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return fail(LBM_EDEVICE, "scratch: device index beyond 63");
+  if (!g_scratch[device]) {
+    double* ptr = nullptr;
+    const hipError_t e = lbm::scratch_address(&ptr);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch[device] = ptr;
+  }
+  *out = g_scratch[device];
+  return LBM_OK;
+}
+
+// The 21 sums of the diagnostic reduction into the ABI struct; sets the
+// handle's instability flag.
+void diag_from_sums(Ctx* c, const double* v, lbm_diag* out) {
+  std::memset(out, 0, sizeof *out);
+  out->step = c->step;
+  out->mass = v[0];
+  out->momentum[0] = v[1];
+  out->momentum[1] = v[2];
+  out->momentum[2] = v[3];
+  out->energy = v[4];
+  out->kinetic_energy = v[5];
+  out->dilatation_sq_sum = v[6];
+  out->u2_sum = v[7];
+  out->cs_sum = v[8];
+  out->rho2_sum = v[9];
+  out->vorticity_sq_sum = v[10];
+  out->dissipation_sum = v[11];
+  for (int a = 0; a < 3; ++a) {
+    out->u_axis_sq_sum[a] = v[12 + a];
+    out->du_axis_sq_sum[a] = v[15 + a];
+  }
+  out->nonfinite = (int64_t)v[18];
+  out->nonpositive = (int64_t)v[19];
+  out->nodes = (int64_t)v[20];
+  c->unstable = out->nonfinite > 0 || out->nonpositive > 0;
+}
+
 }  // namespace
 
 // For the corrector (lbm_nn.hip): the moments of the stored state into
@@ -274,6 +321,13 @@ int lbm_create(lbm_handle* out, int lattice, const int64_t dims[3], double gamma
     return hip_fail(e, "hipGetDevice");
   }
   fill_params(c);
+  {
+    // set-up of the allocation-free diagnostics on this device (the entry
+    // point retries and reports a failure itself)
+    double* sc = nullptr;
+    const std::string keep = g_err;
+    if (scratch_for_device(c->device, &sc) != LBM_OK) g_err = keep;
+  }
   const size_t bytes = word_of(c->precision) * (size_t)c->nm * (size_t)c->ms;
   for (int k = 0; k < 2; ++k) {
     e = hipMalloc(&c->buf[k], bytes);
@@ -406,28 +460,27 @@ int lbm_diagnostics(lbm_handle h, lbm_diag* out) {
   double v[lbm::kNumDiag];
   HIP_OR_FAIL(hipMemcpyAsync(v, c->diag_dev, sizeof v, hipMemcpyDeviceToHost, c->stream), "copy diagnostics");
   HIP_OR_FAIL(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
-  std::memset(out, 0, sizeof *out);
-  out->step = c->step;
-  out->mass = v[0];
-  out->momentum[0] = v[1];
-  out->momentum[1] = v[2];
-  out->momentum[2] = v[3];
-  out->energy = v[4];
-  out->kinetic_energy = v[5];
-  out->dilatation_sq_sum = v[6];
-  out->u2_sum = v[7];
-  out->cs_sum = v[8];
-  out->rho2_sum = v[9];
-  out->vorticity_sq_sum = v[10];
-  out->dissipation_sum = v[11];
-  for (int a = 0; a < 3; ++a) {
-    out->u_axis_sq_sum[a] = v[12 + a];
-    out->du_axis_sq_sum[a] = v[15 + a];
-  }
-  out->nonfinite = (int64_t)v[18];
-  out->nonpositive = (int64_t)v[19];
-  out->nodes = (int64_t)v[20];
-  c->unstable = out->nonfinite > 0 || out->nonpositive > 0;
+  diag_from_sums(c, v, out);
+  return LBM_OK;
+}
+
+int lbm_diagnostics_noalloc(lbm_handle h, lbm_diag* out) {
+  if (!h || !out) return fail(LBM_EINVAL, "lbm_diagnostics_noalloc: NULL argument");
+  Ctx* c = h;
+  if (!c->initialised) return fail(LBM_ESTATE, "lbm_diagnostics_noalloc: call lbm_init_fields first");
+  int rc = select_device(c);
+  if (rc) return rc;
+  const int nblocks = lbm::diag_blocks(*c);
+  if (nblocks < 1 || nblocks > lbm::kMaxDiagBlocks)
+    return fail(LBM_EINVAL, "lbm_diagnostics_noalloc: the reduction needs more partial sums than the scratch holds");
+  double* sc = nullptr;
+  if ((rc = scratch_for_device(c->device, &sc))) return rc;
+  double* final_sums = sc + (size_t)lbm::kMaxDiagBlocks * lbm::kNumDiag;
+  HIP_OR_FAIL(lbm::launch_diag_direct(*c, c->buf[c->cur], sc, nblocks, final_sums), "diagnostics kernel");
+  double v[lbm::kNumDiag];
+  HIP_OR_FAIL(hipMemcpyAsync(v, final_sums, sizeof v, hipMemcpyDeviceToHost, c->stream), "copy diagnostics");
+  HIP_OR_FAIL(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  diag_from_sums(c, v, out);
   return LBM_OK;
 }
 

@@ -84,6 +84,10 @@ struct Ctx {
 };
 
 constexpr int kNumDiag = 21;  // slots of the diagnostic reduction (see lbm_kernels.hip)
+constexpr int kMaxDiagBlocks = 2048;  // work-groups of a diagnostic reduction, at most
+// doubles of the allocation-free diagnostics' device scratch: the block
+// partials of the largest grid, then the final sums
+constexpr int kScratchDoubles = kMaxDiagBlocks * kNumDiag + kNumDiag;
 
 // One box of a batched launch (an entry of the device box table).
 struct BoxEntry {
@@ -116,6 +120,11 @@ hipError_t launch_pattern(const Ctx& c, const void* src, void* dst);
 hipError_t launch_init(const Ctx& c, const double* rho, const double* u, const double* T, void* dst);
 hipError_t launch_fields(const Ctx& c, const void* pops, double* fields);
 hipError_t launch_diag(const Ctx& c, const double* fields, double* partial, int nblocks, double* out);
+// The same sums straight from the populations (no field buffer), and the
+// device address of the current device's allocation-free scratch
+// (kScratchDoubles doubles).
+hipError_t launch_diag_direct(const Ctx& c, const void* pops, double* partial, int nblocks, double* out);
+hipError_t scratch_address(double** out);
 int diag_blocks(const Ctx& c);
 hipError_t launch_validate(const Ctx& c, const double* rho, const double* u, const double* T, double* partial,
                            int nblocks, double* out);

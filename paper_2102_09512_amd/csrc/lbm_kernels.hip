@@ -592,32 +592,69 @@ __global__ void __launch_bounds__(256) init_kernel(const double* __restrict__ rh
 // fields: rho, ux, uy, uz, T, rhoE (each N)
 // ---------------------------------------------------------------------------
 
-template <int D, bool DEV, typename S>
-__global__ void __launch_bounds__(256) fields_kernel(const S* __restrict__ pops, double* __restrict__ fields,
-                                                     long long N, const StepParams p) {
+// Sums of the stored values of node n: s0 = sum f, j = sum c f and, when se
+// is not NULL, *se = sum g (in population order).
+template <int D, typename S>
+__device__ inline void stored_sums(const S* __restrict__ pops, const StepParams& p, long long n, double& s0,
+                                   double* j, double* se) {
   constexpr int Q = lat_q(D);
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  double s0 = 0, jx = 0, jy = 0, jz = 0, se = 0;
+  double jx = 0, jy = 0, jz = 0, e = 0;
+  s0 = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const double v = (double)pops[pop_offset(p, Q, i, n)];
     s0 += v;
-    se += (double)pops[pop_offset(p, Q, i + Q, n)];
+    if (se) e += (double)pops[pop_offset(p, Q, i + Q, n)];
     const int cx = vx(i), cy = vy(i), cz = (D == 3) ? vz(i) : 0;
     if (cx) jx += cx > 0 ? v : -v;
     if (cy) jy += cy > 0 ? v : -v;
     if (cz) jz += cz > 0 ? v : -v;
   }
+  j[0] = jx;
+  j[1] = jy;
+  j[2] = jz;
+  if (se) *se = e;
+}
+
+// rho and u of node n from its stored populations (FP64).
+template <int D, typename S>
+__device__ inline double stored_velocity(const S* __restrict__ pops, const StepParams& p, long long n, double* u) {
+  double s0, j[3];
+  stored_sums<D, S>(pops, p, n, s0, j, nullptr);
   const double rho = p.rho0 + s0;
-  const double ux = (p.j0[0] + jx) / rho, uy = (p.j0[1] + jy) / rho, uz = (D == 3) ? (p.j0[2] + jz) / rho : 0.0;
-  const double rhoE = p.rhoE0 + se;
-  const double e = rhoE / rho - 0.5 * (ux * ux + uy * uy + uz * uz);  // U(T)
-  const double T = p.caloric ? p.T0 + caloric_step(p.Cv, p.cv1, p.cv2, p.T0, e - p.U0) : e * p.inv_Cv;
+  u[0] = (p.j0[0] + j[0]) / rho;
+  u[1] = (p.j0[1] + j[1]) / rho;
+  u[2] = (D == 3) ? (p.j0[2] + j[2]) / rho : 0.0;
+  return rho;
+}
+
+// rho, u, T and rho E of node n from its stored populations (FP64; Eqs.
+// (3)-(7) without streaming).
+template <int D, typename S>
+__device__ inline void stored_fields(const S* __restrict__ pops, const StepParams& p, long long n, double& rho,
+                                     double* u, double& T, double& rhoE) {
+  double s0, j[3], se;
+  stored_sums<D, S>(pops, p, n, s0, j, &se);
+  rho = p.rho0 + s0;
+  u[0] = (p.j0[0] + j[0]) / rho;
+  u[1] = (p.j0[1] + j[1]) / rho;
+  u[2] = (D == 3) ? (p.j0[2] + j[2]) / rho : 0.0;
+  rhoE = p.rhoE0 + se;
+  const double e = rhoE / rho - 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);  // U(T)
+  T = p.caloric ? p.T0 + caloric_step(p.Cv, p.cv1, p.cv2, p.T0, e - p.U0) : e * p.inv_Cv;
+}
+
+template <int D, bool DEV, typename S>
+__global__ void __launch_bounds__(256) fields_kernel(const S* __restrict__ pops, double* __restrict__ fields,
+                                                     long long N, const StepParams p) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  double rho, u[3], T, rhoE;
+  stored_fields<D, S>(pops, p, n, rho, u, T, rhoE);
   fields[n] = rho;
-  fields[N + n] = ux;
-  fields[2 * N + n] = uy;
-  fields[3 * N + n] = uz;
+  fields[N + n] = u[0];
+  fields[2 * N + n] = u[1];
+  fields[3 * N + n] = u[2];
   fields[4 * N + n] = T;
   fields[5 * N + n] = rhoE;
 }
@@ -651,68 +688,121 @@ __device__ inline void block_reduce_store(double (&v)[NV], double* __restrict__ 
 
 __device__ inline int fix_node_axis(int k, int n, int bc) { return fix_coord(k, n, bc); }
 
+// Node indices of the six neighbours x+-1, y+-1, z+-1 of node n (wrap or
+// clamp per axis): nb[0] = x+1, nb[1] = x-1, nb[2] = y+1, nb[3] = y-1,
+// nb[4] = z+1, nb[5] = z-1.
+__device__ inline void neighbours6(const StepParams& p, long long n, long long* nb) {
+  const int nx = p.nx, ny = p.ny, nz = p.nz;
+  const int x = (int)(n % nx);
+  const int y = (int)((n / nx) % ny);
+  const int z = (int)(n / ((long long)nx * ny));
+  auto idx = [&](int xx, int yy, int zz) { return xx + (long long)nx * (yy + (long long)ny * zz); };
+  nb[0] = idx(fix_node_axis(x + 1, nx, p.bc[0]), y, z);
+  nb[1] = idx(fix_node_axis(x - 1, nx, p.bc[0]), y, z);
+  nb[2] = idx(x, fix_node_axis(y + 1, ny, p.bc[1]), z);
+  nb[3] = idx(x, fix_node_axis(y - 1, ny, p.bc[1]), z);
+  nb[4] = idx(x, y, fix_node_axis(z + 1, nz, p.bc[2]));
+  nb[5] = idx(x, y, fix_node_axis(z - 1, nz, p.bc[2]));
+}
+
+// One node's terms of the 21 diagnostic sums (the totals of Eqs. (3)-(5)
+// and the statistics of Sec. III.D), with central differences from the
+// velocities vn[k] of the six neighbours (order of neighbours6).
+template <int D>
+__device__ inline void diag_accumulate(double (&acc)[kNumDiag], const StepParams& p, double rho, const double* u,
+                                       double T, double rhoE, const double (*vn)[3]) {
+  const double ux = u[0], uy = u[1], uz = u[2];
+  // central differences d_b u_a
+  const double dxux = 0.5 * (vn[0][0] - vn[1][0]);
+  const double dyuy = 0.5 * (vn[2][1] - vn[3][1]);
+  const double dzuz = (D == 3) ? 0.5 * (vn[4][2] - vn[5][2]) : 0.0;
+  const double dxuy = 0.5 * (vn[0][1] - vn[1][1]);
+  const double dyux = 0.5 * (vn[2][0] - vn[3][0]);
+  double wx = 0.0, wy = 0.0;
+  if (D == 3) {
+    wx = 0.5 * (vn[2][2] - vn[3][2]) - 0.5 * (vn[4][1] - vn[5][1]);
+    wy = 0.5 * (vn[4][0] - vn[5][0]) - 0.5 * (vn[0][2] - vn[1][2]);
+  }
+  const double wz = dxuy - dyux;
+  const double vort2 = wx * wx + wy * wy + wz * wz;
+  const double div = dxux + dyuy + dzuz;
+  const double uu = ux * ux + uy * uy + uz * uz;
+  const bool finite = isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy) && isfinite(uz);
+  const double mu = (p.visc_exp == 0.0) ? p.mu0 : p.mu0 * pow(T * p.inv_Tref, p.visc_exp);
+  acc[0] += rho;
+  acc[1] += rho * ux;
+  acc[2] += rho * uy;
+  acc[3] += rho * uz;
+  acc[4] += rhoE;
+  acc[5] += 0.5 * rho * uu;
+  acc[6] += div * div;
+  acc[7] += uu;
+  double gam = p.gamma;  // C_p / C_v at T (Mayer: C_p = C_v + 1)
+  if (p.caloric) {
+    const double cvT = caloric_cv(p.Cv, p.cv1, p.cv2, T);
+    gam = (cvT + 1.0) / cvT;
+  }
+  acc[8] += sqrt(gam * T);
+  acc[9] += rho * rho;
+  acc[10] += vort2;
+  acc[11] += mu * vort2;
+  acc[12] += ux * ux;
+  acc[13] += uy * uy;
+  acc[14] += uz * uz;
+  acc[15] += dxux * dxux;
+  acc[16] += dyuy * dyuy;
+  acc[17] += dzuz * dzuz;
+  acc[18] += finite ? 0.0 : 1.0;
+  acc[19] += (rho <= 0.0 || T <= 0.0) ? 1.0 : 0.0;
+  acc[20] += 1.0;
+}
+
+// Diagnostics from the field buffer F (rho, u_x, u_y, u_z, T, rho E planes).
 template <int D>
 __global__ void __launch_bounds__(256) diag_kernel(const double* __restrict__ F, double* __restrict__ partial,
                                                    long long N, const StepParams p) {
   double acc[kNumDiag];
 #pragma unroll
   for (int j = 0; j < kNumDiag; ++j) acc[j] = 0.0;
-  const int nx = p.nx, ny = p.ny, nz = p.nz;
   for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
-    const int x = (int)(n % nx);
-    const int y = (int)((n / nx) % ny);
-    const int z = (int)(n / ((long long)nx * ny));
-    auto at = [&](int comp, int xx, int yy, int zz) {
-      return F[(long long)comp * N + xx + (long long)nx * (yy + (long long)ny * zz)];
-    };
-    const int xp = fix_node_axis(x + 1, nx, p.bc[0]), xm = fix_node_axis(x - 1, nx, p.bc[0]);
-    const int yp = fix_node_axis(y + 1, ny, p.bc[1]), ym = fix_node_axis(y - 1, ny, p.bc[1]);
-    const int zp = fix_node_axis(z + 1, nz, p.bc[2]), zm = fix_node_axis(z - 1, nz, p.bc[2]);
-    const double rho = F[n], ux = F[N + n], uy = F[2 * N + n], uz = F[3 * N + n], T = F[4 * N + n],
-                 rhoE = F[5 * N + n];
-    // central differences d_b u_a
-    const double dxux = 0.5 * (at(1, xp, y, z) - at(1, xm, y, z));
-    const double dyuy = 0.5 * (at(2, x, yp, z) - at(2, x, ym, z));
-    const double dzuz = (D == 3) ? 0.5 * (at(3, x, y, zp) - at(3, x, y, zm)) : 0.0;
-    const double dxuy = 0.5 * (at(2, xp, y, z) - at(2, xm, y, z));
-    const double dyux = 0.5 * (at(1, x, yp, z) - at(1, x, ym, z));
-    double wx = 0.0, wy = 0.0;
-    if (D == 3) {
-      wx = 0.5 * (at(3, x, yp, z) - at(3, x, ym, z)) - 0.5 * (at(2, x, y, zp) - at(2, x, y, zm));
-      wy = 0.5 * (at(1, x, y, zp) - at(1, x, y, zm)) - 0.5 * (at(3, xp, y, z) - at(3, xm, y, z));
+    long long nb[6];
+    neighbours6(p, n, nb);
+    double vn[6][3];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) vn[k][a] = F[(long long)(1 + a) * N + nb[k]];
+    const double u[3] = {F[N + n], F[2 * N + n], F[3 * N + n]};
+    diag_accumulate<D>(acc, p, F[n], u, F[4 * N + n], F[5 * N + n], vn);
+  }
+  block_reduce_store<kNumDiag>(acc, partial + (long long)blockIdx.x * kNumDiag);
+}
+
+// The same sums straight from the stored populations: every node forms its
+// own fields and its neighbours' velocities from the populations with the
+// arithmetic of fields_kernel, so the terms, and with the same grid the
+// sums, are those of fields_kernel + diag_kernel; no field buffer is needed.
+template <int D, typename S>
+__global__ void __launch_bounds__(256) diag_direct_kernel(const S* __restrict__ pops, double* __restrict__ partial,
+                                                          long long N, const StepParams p) {
+  double acc[kNumDiag];
+#pragma unroll
+  for (int j = 0; j < kNumDiag; ++j) acc[j] = 0.0;
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+    long long nb[6];
+    neighbours6(p, n, nb);
+    double vn[6][3];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      if (D == 2 && k >= 4) {  // no z neighbours: the (unused) z differences see the node itself
+        vn[k][0] = vn[k][1] = vn[k][2] = 0.0;
+        continue;
+      }
+      stored_velocity<D, S>(pops, p, nb[k], vn[k]);
     }
-    const double wz = dxuy - dyux;
-    const double vort2 = wx * wx + wy * wy + wz * wz;
-    const double div = dxux + dyuy + dzuz;
-    const double uu = ux * ux + uy * uy + uz * uz;
-    const bool finite = isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy) && isfinite(uz);
-    const double mu = (p.visc_exp == 0.0) ? p.mu0 : p.mu0 * pow(T * p.inv_Tref, p.visc_exp);
-    acc[0] += rho;
-    acc[1] += rho * ux;
-    acc[2] += rho * uy;
-    acc[3] += rho * uz;
-    acc[4] += rhoE;
-    acc[5] += 0.5 * rho * uu;
-    acc[6] += div * div;
-    acc[7] += uu;
-    double gam = p.gamma;  // C_p / C_v at T (Mayer: C_p = C_v + 1)
-    if (p.caloric) {
-      const double cvT = caloric_cv(p.Cv, p.cv1, p.cv2, T);
-      gam = (cvT + 1.0) / cvT;
-    }
-    acc[8] += sqrt(gam * T);
-    acc[9] += rho * rho;
-    acc[10] += vort2;
-    acc[11] += mu * vort2;
-    acc[12] += ux * ux;
-    acc[13] += uy * uy;
-    acc[14] += uz * uz;
-    acc[15] += dxux * dxux;
-    acc[16] += dyuy * dyuy;
-    acc[17] += dzuz * dzuz;
-    acc[18] += finite ? 0.0 : 1.0;
-    acc[19] += (rho <= 0.0 || T <= 0.0) ? 1.0 : 0.0;
-    acc[20] += 1.0;
+    double rho, u[3], T, rhoE;
+    stored_fields<D, S>(pops, p, n, rho, u, T, rhoE);
+    diag_accumulate<D>(acc, p, rho, u, T, rhoE, vn);
   }
   block_reduce_store<kNumDiag>(acc, partial + (long long)blockIdx.x * kNumDiag);
 }
@@ -1137,7 +1227,43 @@ hipError_t launch_fields(const Ctx& c, const void* pops, double* fields) {
 
 int diag_blocks(const Ctx& c) {
   const long long want = (c.N + 255) / 256;
-  return (int)(want < 2048 ? want : 2048);
+  return (int)(want < kMaxDiagBlocks ? want : kMaxDiagBlocks);
+}
+
+// Device memory of the allocation-free diagnostics (lbm_diagnostics_noalloc):
+// the per-block partial sums and the final sums, kScratchDoubles doubles
+// (344 KB) on every device the library runs on, held until the process
+// ends.  Host code never uses this name as an address: scratch_address
+// returns the device address of the current device's copy.
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+hipError_t scratch_address(double** out) {
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  *out = e == hipSuccess ? static_cast<double*>(ptr) : nullptr;
+  return e;
+}
+
+hipError_t launch_diag_direct(const Ctx& c, const void* pops, double* partial, int nblocks, double* out) {
+  if (c.lattice == 3) {
+    if (c.precision == LBM_FP64)
+      hipLaunchKernelGGL((diag_direct_kernel<3, double>), dim3(nblocks), dim3(256), 0, c.stream,
+                         static_cast<const double*>(pops), partial, (long long)c.N, c.sp);
+    else
+      hipLaunchKernelGGL((diag_direct_kernel<3, float>), dim3(nblocks), dim3(256), 0, c.stream,
+                         static_cast<const float*>(pops), partial, (long long)c.N, c.sp);
+  } else {
+    if (c.precision == LBM_FP64)
+      hipLaunchKernelGGL((diag_direct_kernel<2, double>), dim3(nblocks), dim3(256), 0, c.stream,
+                         static_cast<const double*>(pops), partial, (long long)c.N, c.sp);
+    else
+      hipLaunchKernelGGL((diag_direct_kernel<2, float>), dim3(nblocks), dim3(256), 0, c.stream,
+                         static_cast<const float*>(pops), partial, (long long)c.N, c.sp);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((final_reduce_kernel<kNumDiag>), dim3(1), dim3(256), 0, c.stream, partial, nblocks, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_diag(const Ctx& c, const double* fields, double* partial, int nblocks, double* out) {

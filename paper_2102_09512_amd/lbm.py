@@ -72,6 +72,7 @@ def _load():
     L.lbm_step.argtypes = [vp, i64]
     L.lbm_moments.argtypes = [vp, vp, vp, vp, C.c_int]
     L.lbm_diagnostics.argtypes = [vp, C.POINTER(lbm_diag)]
+    L.lbm_diagnostics_noalloc.argtypes = [vp, C.POINTER(lbm_diag)]
     L.lbm_state_bytes.argtypes = [vp]
     L.lbm_state_bytes.restype = C.c_size_t
     L.lbm_get_state.argtypes = [vp, vp, C.c_size_t, C.c_int]
@@ -113,7 +114,7 @@ def _load():
     L.lbm_batch_tune.argtypes = [vp, C.c_int, dp]
     L.lbm_batch_step.argtypes = [vp, i64, C.c_int]
     for name in ("lbm_create", "lbm_destroy", "lbm_set_stream", "lbm_init_fields", "lbm_step", "lbm_moments",
-                 "lbm_diagnostics", "lbm_get_state", "lbm_set_state", "lbm_device_copy", "lbm_batch_create",
+                 "lbm_diagnostics", "lbm_diagnostics_noalloc", "lbm_get_state", "lbm_set_state", "lbm_device_copy", "lbm_batch_create",
                  "lbm_batch_destroy", "lbm_batch_set_stream", "lbm_batch_set_tile", "lbm_batch_get_tile",
                  "lbm_get_tile", "lbm_get_dims", "lbm_pattern_reference", "lbm_batch_tune", "lbm_batch_step", "lbm_fields_add", "lbm_filter_moments", "lbm_nn_create",
                  "lbm_nn_destroy", "lbm_nn_set_stream", "lbm_nn_set_params", "lbm_nn_get_params", "lbm_nn_get_grads",
@@ -288,14 +289,24 @@ def lbm_moments(h, rho=None, u=None, T=None):
     return rho, u, T
 
 
-def lbm_diagnostics(h) -> dict:
-    d = lbm_diag()
-    _check(_L.lbm_diagnostics(h, C.byref(d)))
+def _diag_dict(d) -> dict:
     out = {}
     for name, _ in lbm_diag._fields_:
         v = getattr(d, name)
         out[name] = list(v) if isinstance(v, C.Array) else v
     return out
+
+
+def lbm_diagnostics(h) -> dict:
+    d = lbm_diag()
+    _check(_L.lbm_diagnostics(h, C.byref(d)))
+    return _diag_dict(d)
+
+
+def lbm_diagnostics_noalloc(h) -> dict:
+    d = lbm_diag()
+    _check(_L.lbm_diagnostics_noalloc(h, C.byref(d)))
+    return _diag_dict(d)
 
 
 def lbm_get_tile(h):
