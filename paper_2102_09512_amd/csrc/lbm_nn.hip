@@ -34,6 +34,7 @@ namespace lbmnn {
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f16v __attribute__((ext_vector_type(16)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 struct Grid {
   int nx, ny, nz;
@@ -94,18 +95,13 @@ __device__ inline int swizzle(int c, int hx) {
 // [v][32], may be null): zero where mask <= 0 (the derivative of the ReLU that
 // produced it).  bias may be null; it holds cout values.
 // Requires nx % 32 == 0, ny % 4 == 0, nz % 4 == 0; grid = tiles.
-template <int CIN, bool OUT_PLANAR>
-__global__ void __launch_bounds__(64 * kW) conv_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ wp,
-                                                   const float* __restrict__ bias, int relu,
-                                                   const __bf16* __restrict__ mask, void* __restrict__ out, int cout,
-                                                   const Grid g, int V) {
-  constexpr int CH = CIN / 8;  // 16-byte chunks per node
-  __shared__ __attribute__((aligned(16))) __bf16 tile[kHZ * kHY * kHX * CIN];
-  const int tx = g.nx / kTX, ty = g.ny / kTY;
-  const int b = xcd_tile(blockIdx.x, gridDim.x);
-  const int x0 = (b % tx) * kTX, y0 = ((b / tx) % ty) * kTY, z0 = (b / (tx * ty)) * kTZ;
-  // Staging: every thread issues all its loads before its first LDS write,
-  // so the tile costs one memory latency instead of one per chunk.
+// Stages the input tile of output tile (x0, y0, z0) with its one-node
+// periodic halo in LDS, swizzled (every thread issues all its loads before
+// its first LDS write, so the tile costs one memory latency instead of one
+// per chunk), and waits for the work-group.
+template <int CIN>
+__device__ inline void stage_tile(const __bf16* __restrict__ in, __bf16* tile, const Grid& g, int x0, int y0, int z0) {
+  constexpr int CH = CIN / 8;                           // 16-byte chunks per node
   constexpr int NCH = kHZ * kHY * kHX * CH;            // 16-byte chunks of the halo tile
   constexpr int NIT = (NCH + 64 * kW - 1) / (64 * kW);  // chunks per thread
   bf8 stage[NIT];
@@ -128,34 +124,15 @@ __global__ void __launch_bounds__(64 * kW) conv_kernel(const __bf16* __restrict_
     }
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int r = lane & 31, half = lane >> 5;
-  float bo[16];  // loaded before the tap loop, whose time covers their latency
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int c = 8 * (i >> 2) + 4 * half + (i & 3);
-    bo[i] = bias && c < cout ? bias[c] : 0.f;
-  }
-  f16v acc[kR] = {};
-  // Fully unrolled: the compiler hoists later taps' loads over earlier taps'
-  // matrix-core work (4.5% faster than a rolled loop).
-#pragma unroll
-  for (int t = 0; t < 27; ++t) {
-    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-    const int hx = r + dx + 1;
-    const __bf16* col = tile + hx * CIN;
-#pragma unroll
-    for (int cc = 0; cc < CIN / 16; ++cc) {
-      const bf8 a = *(const bf8*)(wp + ((size_t)(t * (CIN / 16) + cc) * 32 + r) * 16 + 8 * half);
-      const int off = swizzle<CIN>(2 * cc + half, hx) * 8;
-#pragma unroll
-      for (int j = 0; j < kR; ++j) {
-        const int q = w * kR + j, hy = q % kTY + dy + 1, hz = q / kTY + dz + 1;
-        const bf8 bv = *(const bf8*)(col + (hz * kHY + hy) * kHX * CIN + off);
-        acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[j], 0, 0, 0);
-      }
-    }
-  }
+}
+
+// Bias, ReLU, ReLU-derivative mask and store of a wavefront's kR output rows
+// (32 x 32 accumulator layout: accumulator i of lane l holds output channel
+// 8(i/4) + 4(l/32) + i%4 of node x0 + l%32).
+template <bool OUT_PLANAR>
+__device__ inline void conv_epilogue(const f16v* acc, const float* bo, int relu, const __bf16* __restrict__ mask,
+                                     void* __restrict__ out, int cout, const Grid& g, int V, int x0, int y0, int z0,
+                                     int w, int r, int half) {
 #pragma unroll
   for (int j = 0; j < kR; ++j) {
     const int q = w * kR + j;
@@ -189,6 +166,187 @@ __global__ void __launch_bounds__(64 * kW) conv_kernel(const __bf16* __restrict_
       }
     }
   }
+}
+
+template <int CIN, bool OUT_PLANAR>
+__global__ void __launch_bounds__(64 * kW) conv_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ wp,
+                                                   const float* __restrict__ bias, int relu,
+                                                   const __bf16* __restrict__ mask, void* __restrict__ out, int cout,
+                                                   const Grid g, int V) {
+  __shared__ __attribute__((aligned(16))) __bf16 tile[kHZ * kHY * kHX * CIN];
+  const int tx = g.nx / kTX, ty = g.ny / kTY;
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (b % tx) * kTX, y0 = ((b / tx) % ty) * kTY, z0 = (b / (tx * ty)) * kTZ;
+  stage_tile<CIN>(in, tile, g, x0, y0, z0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 31, half = lane >> 5;
+  float bo[16];  // loaded before the tap loop, whose time covers their latency
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int c = 8 * (i >> 2) + 4 * half + (i & 3);
+    bo[i] = bias && c < cout ? bias[c] : 0.f;
+  }
+  f16v acc[kR] = {};
+  // Wave w owns the kTY output rows of plane z = w of the tile.  For one
+  // (dz, dx) pair and 16-channel block, each of the kTY + 2 input rows of
+  // the halo column is read from LDS once and feeds the (up to three)
+  // output rows it reaches through the taps dy = -1, 0, 1, each with its own
+  // weights: half the LDS reads of one read per tap and row.  Fully
+  // unrolled, so the compiler hoists later loads over earlier matrix-core
+  // work.
+  static_assert(kR == kTY && kW == kTZ, "a wavefront owns one plane of the tile");
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int hz = w + dz + 1;
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int hx = r + dx + 1;
+      const __bf16* col = tile + hx * CIN + hz * kHY * kHX * CIN;
+#pragma unroll
+      for (int cc = 0; cc < CIN / 16; ++cc) {
+        bf8 a[3];  // weights of the taps (dx, dy, dz), dy = -1, 0, 1
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int t = (dx + 1) + 3 * k + 9 * (dz + 1);
+          a[k] = *(const bf8*)(wp + ((size_t)(t * (CIN / 16) + cc) * 32 + r) * 16 + 8 * half);
+        }
+        const int off = swizzle<CIN>(2 * cc + half, hx) * 8;
+#pragma unroll
+        for (int hy = 0; hy < kTY + 2; ++hy) {
+          const bf8 bv = *(const bf8*)(col + hy * kHX * CIN + off);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const int j = hy - k;  // output row reached through dy = k - 1
+            if (j >= 0 && j < kTY) acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[k], bv, acc[j], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  conv_epilogue<OUT_PLANAR>(acc, bo, relu, mask, out, cout, g, V, x0, y0, z0, w, r, half);
+}
+
+// Input layer of at most 8 channels (the corrector's 5: rho, u, T): the
+// input activations hold 16 channels per node of which the first 8 are
+// staged (16 bytes per node), and the matrix-core K dimension of 16 takes two
+// taps at a time, 8 channels each: lane half h supplies tap 2p + h of pair p.
+// 14 products per output row instead of 27.  wq[p][o][k]: k < 8 channel k
+// of tap 2p, k >= 8 channel k - 8 of tap 2p + 1 (tap 27 does not exist: its
+// weights are zero and its B operand repeats tap 26).  Output as
+// conv_kernel (bf16 [v][32]).
+__global__ void __launch_bounds__(64 * kW) conv_pair_kernel(const __bf16* __restrict__ in,
+                                                            const __bf16* __restrict__ wq,
+                                                            const float* __restrict__ bias, int relu,
+                                                            __bf16* __restrict__ out, int cout, const Grid g, int V) {
+  constexpr int NN = kHZ * kHY * kHX;  // halo nodes; one 16-byte chunk each
+  __shared__ __attribute__((aligned(16))) __bf16 tile[NN * 8];
+  const int tx = g.nx / kTX, ty = g.ny / kTY;
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (b % tx) * kTX, y0 = ((b / tx) % ty) * kTY, z0 = (b / (tx * ty)) * kTZ;
+  {
+    constexpr int NIT = (NN + 64 * kW - 1) / (64 * kW);
+    bf8 stage[NIT];
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int node = threadIdx.x + k * 64 * kW;
+      if (node < NN) {
+        const int hx = node % kHX, hy = (node / kHX) % kHY, hz = node / (kHX * kHY);
+        const int gx = wrap(x0 + hx - 1, g.nx), gy = wrap(y0 + hy - 1, g.ny), gz = wrap(z0 + hz - 1, g.nz);
+        stage[k] = *(const bf8*)(in + (size_t)(gx + g.nx * (gy + g.ny * gz)) * 16);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int node = threadIdx.x + k * 64 * kW;
+      if (node < NN) *(bf8*)(tile + node * 8) = stage[k];
+    }
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 31, half = lane >> 5;
+  float bo[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int c = 8 * (i >> 2) + 4 * half + (i & 3);
+    bo[i] = bias && c < cout ? bias[c] : 0.f;
+  }
+  f16v acc[kR] = {};
+#pragma unroll
+  for (int p = 0; p < 14; ++p) {
+    const bf8 a = *(const bf8*)(wq + ((size_t)p * 32 + r) * 16 + 8 * half);
+    const int t = min(2 * p + half, 26);
+    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+    const __bf16* col = tile + (r + dx + 1) * 8;
+#pragma unroll
+    for (int j = 0; j < kR; ++j) {
+      const int q = w * kR + j, hy = q % kTY + dy + 1, hz = q / kTY + dz + 1;
+      const bf8 bv = *(const bf8*)(col + (hz * kHY + hy) * kHX * 8);
+      acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[j], 0, 0, 0);
+    }
+  }
+  conv_epilogue<false>(acc, bo, relu, nullptr, out, cout, g, V, x0, y0, z0, w, r, half);
+}
+
+// Output layer with at most 16 channels (the corrector's 3): the same
+// convolution on v_mfma_f32_16x16x32_bf16 (A 16 x 32, B 32 x 16; lane l
+// supplies A[l%16][8(l/16) .. +7] and B[8(l/16) .. +7][l%16] and holds
+// D[4(l/16) .. +3][l%16]), with A = weights (m = output channel, padded to
+// 16 instead of 32, k = the 32 input channels of one tap) and B = the
+// activations of 16 nodes: half the matrix-core work of conv_kernel for such
+// a layer.  FP32 planes out[o][v] for o < cout.  wn[t][o][i] (o < 16,
+// i < 32).  Same tile and staging as conv_kernel; input width 32.
+__global__ void __launch_bounds__(64 * kW) conv_narrow_kernel(const __bf16* __restrict__ in,
+                                                              const __bf16* __restrict__ wn,
+                                                              const float* __restrict__ bias,
+                                                              float* __restrict__ out, int cout, const Grid g, int V) {
+  __shared__ __attribute__((aligned(16))) __bf16 tile[kHZ * kHY * kHX * 32];
+  const int tx = g.nx / kTX, ty = g.ny / kTY;
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (b % tx) * kTX, y0 = ((b / tx) % ty) * kTY, z0 = (b / (tx * ty)) * kTZ;
+  stage_tile<32>(in, tile, g, x0, y0, z0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n16 = lane & 15, grp = lane >> 4;
+  float bo[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) bo[v] = bias && 4 * grp + v < cout ? bias[4 * grp + v] : 0.f;
+  f4v acc[kTY][2] = {};
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int hz = w + dz + 1;
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      bf8 a[3];  // taps (dx, dy, dz), dy = -1, 0, 1: A[o = l%16][i = 8(l/16) + j]
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int t = (dx + 1) + 3 * k + 9 * (dz + 1);
+        a[k] = *(const bf8*)(wn + ((size_t)t * 16 + n16) * 32 + 8 * grp);
+      }
+#pragma unroll
+      for (int hy = 0; hy < kTY + 2; ++hy) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int hx = 16 * h + n16 + dx + 1;
+          const bf8 bv = *(const bf8*)(tile + ((hz * kHY + hy) * kHX + hx) * 32 + swizzle<32>(grp, hx) * 8);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const int j = hy - k;
+            if (j >= 0 && j < kTY) acc[j][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[k], bv, acc[j][h], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kTY; ++j)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int v = (x0 + 16 * h + n16) + g.nx * ((y0 + j) + g.ny * (z0 + w));
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = 4 * grp + q;
+        if (c < cout) out[(size_t)c * V + v] = acc[j][h][q] + bo[q];
+      }
+    }
 }
 
 // Weight and bias gradients of one layer, per work-group partial sums:
@@ -386,13 +544,26 @@ __global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ p, const 
 // bf16 copies of one layer's FP32 weights W[t][i][o] (cin x cout):
 // wp[t][i/16][o][i%16] (CINP padded inputs, 32 outputs) and
 // wb[t][o/16][i][o%16] = W[26 - t][i][o] (32 padded outputs as inputs, 32 rows)
+// and, for an output layer of at most 16 channels, wn[t][o][i] = W[t][i][o]
+// (16 padded outputs, 32 padded inputs); for an input layer of at most 8
+// channels, wq[p][o][k] (taps 2p and 2p + 1, 8 channels each)
 __global__ void __launch_bounds__(256) pack_weights_kernel(const float* __restrict__ W, int cin, int cout, int cinp,
-                                                           __bf16* __restrict__ wp, __bf16* __restrict__ wb) {
+                                                           __bf16* __restrict__ wp, __bf16* __restrict__ wb,
+                                                           __bf16* __restrict__ wn, __bf16* __restrict__ wq) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < 27 * cinp * 32) {  // wp element (t, cc, o, k)
     const int k = e % 16, o = (e / 16) % 32, cc = (e / 512) % (cinp / 16), t = e / (512 * (cinp / 16));
     const int i = cc * 16 + k;
     wp[e] = (__bf16)(i < cin && o < cout ? W[((size_t)t * cin + i) * cout + o] : 0.f);
+  }
+  if (wq && e < 14 * 32 * 16) {  // wq element (p, o, k): tap 2p + k / 8, channel k % 8
+    const int k = e % 16, o = (e / 16) % 32, p = e / 512;
+    const int t = 2 * p + k / 8, i = k % 8;
+    wq[e] = (__bf16)(t < 27 && i < cin && o < cout ? W[((size_t)t * cin + i) * cout + o] : 0.f);
+  }
+  if (wn && e < 27 * 16 * 32) {  // wn element (t, o, i)
+    const int i = e % 32, o = (e / 32) % 16, t = e / 512;
+    wn[e] = (__bf16)(i < cin && o < cout ? W[((size_t)t * cin + i) * cout + o] : 0.f);
   }
   if (wb && e < 27 * 32 * 32) {  // wb element (t, oc, i, k): input channel of the mirrored conv = o
     const int k = e % 16, i = (e / 16) % 32, oc = (e / 512) % 2, t = e / 1024;
@@ -457,6 +628,8 @@ struct Layer {
   int cin, cout, cinp;          // channels, padded input channels (16 or 32)
   long long w_off, b_off;       // offsets in the parameter vector
   __bf16 *wp = nullptr, *wb = nullptr;
+  __bf16* wn = nullptr;         // output layer of <= 16 channels from 32 inputs: weights for conv_narrow_kernel
+  __bf16* wq = nullptr;         // input layer of <= 8 channels (not the last): weights for conv_pair_kernel
 };
 
 }  // namespace
@@ -501,7 +674,7 @@ int nn_pack_weights(lbm_nn n) {
     Layer& ly = n->layers[l];
     const int total = 27 * 32 * 32 > 27 * ly.cinp * 32 ? 27 * 32 * 32 : 27 * ly.cinp * 32;
     hipLaunchKernelGGL(lbmnn::pack_weights_kernel, dim3((total + 255) / 256), dim3(256), 0, n->stream,
-                       n->params + ly.w_off, ly.cin, ly.cout, ly.cinp, ly.wp, l > 0 ? ly.wb : nullptr);
+                       n->params + ly.w_off, ly.cin, ly.cout, ly.cinp, ly.wp, l > 0 ? ly.wb : nullptr, ly.wn, ly.wq);
     NN_HIP(hipGetLastError(), "pack weights");
   }
   return LBM_OK;
@@ -527,7 +700,17 @@ int nn_forward(lbm_nn n, const float* x) {
     const bool last = l == n->L - 1;
     const float* b = n->params + ly.b_off;
     hipError_t e;
-    if (ly.cinp == 16)
+    if (last && ly.wn) {
+      const int blocks = (n->g.nx / lbmnn::kTX) * (n->g.ny / lbmnn::kTY) * (n->g.nz / lbmnn::kTZ);
+      hipLaunchKernelGGL(lbmnn::conv_narrow_kernel, dim3(blocks), dim3(64 * lbmnn::kW), 0, n->stream, n->act[l], ly.wn,
+                         b, n->y, ly.cout, n->g, n->V);
+      e = hipGetLastError();
+    } else if (ly.wq) {
+      const int blocks = (n->g.nx / lbmnn::kTX) * (n->g.ny / lbmnn::kTY) * (n->g.nz / lbmnn::kTZ);
+      hipLaunchKernelGGL(lbmnn::conv_pair_kernel, dim3(blocks), dim3(64 * lbmnn::kW), 0, n->stream, n->act[l], ly.wq,
+                         b, 1, n->act[l + 1], ly.cout, n->g, n->V);
+      e = hipGetLastError();
+    } else if (ly.cinp == 16)
       e = last ? conv<16, true>(n, n->act[l], ly.wp, b, 0, nullptr, n->y, ly.cout)
                : conv<16, false>(n, n->act[l], ly.wp, b, 1, nullptr, n->act[l + 1], ly.cout);
     else
@@ -603,9 +786,12 @@ int lbm_nn_create(lbm_nn* out, int layers, const int* channels, const int64_t di
   alloc((void**)&n->loss_acc, sizeof(double));
   alloc((void**)&n->fld, sizeof(float) * 16 * (size_t)V);
   alloc((void**)&n->dfld, sizeof(double) * 10 * (size_t)V);
-  for (Layer& ly : n->layers) {
+  for (int l = 0; l < layers; ++l) {
+    Layer& ly = n->layers[l];
     alloc((void**)&ly.wp, sizeof(__bf16) * 27 * ly.cinp * 32);
     alloc((void**)&ly.wb, sizeof(__bf16) * 27 * 32 * 32);
+    if (l == layers - 1 && ly.cinp == 32 && ly.cout <= 16) alloc((void**)&ly.wn, sizeof(__bf16) * 27 * 16 * 32);
+    if (l == 0 && layers > 1 && ly.cin <= 8) alloc((void**)&ly.wq, sizeof(__bf16) * 14 * 32 * 16);
   }
   if (rc == LBM_OK) {
     std::vector<float> mean(16, 0.f), one(32, 1.f);
@@ -646,6 +832,8 @@ int lbm_nn_destroy(lbm_nn n) {
   for (Layer& ly : n->layers) {
     if (ly.wp) (void)hipFree(ly.wp);
     if (ly.wb) (void)hipFree(ly.wb);
+    if (ly.wn) (void)hipFree(ly.wn);
+    if (ly.wq) (void)hipFree(ly.wq);
   }
   delete n;
   return LBM_OK;
