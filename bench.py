@@ -147,10 +147,76 @@ def run_ensemble(args, torch, lbm, dev):
         lbm.lbm_set_stream(h, stream)
         lbm.lbm_init_fields(h, *(torch.from_numpy(a).to(dev) for a in b["fields"]))
         hs.append(h)
+    # each box stepped on its own (one launch per box per step), for comparison
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    solo_ms = 0.0
+    for h in hs:
+        lbm.lbm_step(h, 2)
+        e0.record(stream)
+        lbm.lbm_step(h, 10)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        solo_ms += e0.elapsed_time(e1) / 10
     batch = lbm.lbm_batch_create(hs)
     tuned_ms = lbm.lbm_batch_tune(batch, 20)
     tile = lbm.lbm_batch_get_tile(batch)
-    _log(f"[bench] {len(hs)} boxes, {N} nodes; tuned tile {tile} ({tuned_ms:.3f} ms per step)")
+    persistent = lbm.lbm_batch_get_persistent(batch)
+    # the tuned tile in both launch forms, timed the same way (one step = one launch)
+    form_ms = {}
+    for form in (False, True):
+        lbm.lbm_batch_set_persistent(batch, form)
+        lbm.lbm_batch_step(batch, 4, 0)
+        e0.record(stream)
+        lbm.lbm_batch_step(batch, 20, 0)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        form_ms["persistent" if form else "per_tile"] = round(e0.elapsed_time(e1) / 20, 4)
+    # work-items of the ragged x tiles that hold no node (D2Q9 tiles are bx x 1)
+    def idle_of(bx):
+        return 1.0 - N / sum(-(-b["dims"][0] // bx) * bx * b["dims"][1] for b in boxes)
+
+    idle = idle_of(tile[0])
+    sweep = []
+    if args.ensemble_sweep:
+        # every compiled tile width and march chunk in both launch forms: time per launch, work-groups,
+        # idle work-items, rows read per node (each chunk of c rows reads c + 2)
+        for bx in (64, 128, 256):
+            for chunk in (4, 8, 16, 32, 64):
+                for form in (False, True):
+                    lbm.lbm_batch_set_persistent(batch, False)
+                    lbm.lbm_batch_set_tile(batch, (bx, 1, chunk))
+                    lbm.lbm_batch_set_persistent(batch, form)
+                    lbm.lbm_batch_step(batch, 4, 0)
+                    e0.record(stream)
+                    lbm.lbm_batch_step(batch, 20, 0)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    ms = e0.elapsed_time(e1) / 20
+                    wgs = sum(-(-b["dims"][0] // bx) * -(-b["dims"][1] // chunk) for b in boxes)
+                    rows = sum(-(-b["dims"][0] // bx) * bx * (b["dims"][1] + 2 * -(-b["dims"][1] // chunk))
+                               for b in boxes) / sum(-(-b["dims"][0] // bx) * bx * b["dims"][1] for b in boxes)
+                    sweep.append({"bx": bx, "chunk": chunk, "form": "persistent" if form else "per_tile",
+                                  "ms": round(ms, 4), "work_groups": wgs, "idle": round(idle_of(bx), 4),
+                                  "rows_read_per_row": round(rows, 4),
+                                  "algorithmic_gbs": round(144 * N / ms / 1e6, 1)})
+                    _log(f"[bench] sweep {sweep[-1]}")
+        lbm.lbm_batch_set_persistent(batch, False)
+        lbm.lbm_batch_set_tile(batch, tile)
+    lbm.lbm_batch_set_persistent(batch, persistent)
+    # the library's copy kernel moving the same bytes as one step (half read, half written)
+    half = N * 72
+    ca = torch.empty(half // 4, dtype=torch.float32, device=dev)
+    cb = torch.empty_like(ca)
+    lbm.lbm_device_copy(cb, ca, half, stream)
+    e0.record(stream)
+    for _ in range(20):
+        lbm.lbm_device_copy(cb, ca, half, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * half / (e0.elapsed_time(e1) / 20) / 1e6
+    del ca, cb
+    _log(f"[bench] {len(hs)} boxes, {N} nodes; tuned tile {tile} persistent={persistent} ({tuned_ms:.3f} ms per step); "
+         f"forms {form_ms}; boxes one by one {solo_ms:.3f} ms per step; idle work-items {idle:.4f}")
     lbm.lbm_batch_step(batch, args.warmup, 0)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -186,14 +252,22 @@ def run_ensemble(args, torch, lbm, dev):
         "config": {"workload": "ensemble of 64 periodic D2Q9 boxes {64..512}^2 decaying-turbulence "
                                "Ma_t~U[0.1,0.6] fp32-storage", "lattice": "D2Q9", "boxes": len(boxes),
                    "nodes": N, "bytes_per_node_update": bytes_per_node, "tile": list(tile),
+                   "launch": "persistent" if persistent else "per_tile",
                    "graph_steps": args.graph_steps, "parallelism": "single GPU"},
+        "launch_forms_ms_per_step": form_ms,
+        "boxes_one_by_one_ms_per_step": round(solo_ms, 4),
+        "idle_work_item_fraction": round(idle, 4),
+        "copy_same_bytes_gbs": round(copy_gbs, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
-                     "kernel": "batch_step_kernel", "avg_step_ms": round(gpu_s / args.steps * 1e3, 4),
+                     "kernel": "batch_persistent_kernel" if persistent else "batch_step_kernel",
+                     "avg_step_ms": round(gpu_s / args.steps * 1e3, 4),
                      "algorithmic_bytes_per_launch": bytes_per_node * N},
         "kernel_source": kernel_source_hash(),
         "boxes_with_bad_nodes": bad,
     }
+    if sweep:
+        out["tile_sweep"] = sweep
     if not args.no_cpu_baseline:
         import oracle
 
@@ -413,6 +487,8 @@ def main():
     ap.add_argument("--eval-seeds", type=int, default=4, help="learned corrector: held-out seeds")
     ap.add_argument("--lr", type=float, default=1e-3, help="learned corrector: Adam learning rate")
     ap.add_argument("--graph-steps", type=int, default=50, help="ensemble2d: steps per captured HIP graph")
+    ap.add_argument("--ensemble-sweep", action="store_true",
+                    help="ensemble2d: also time every tile width, march chunk and launch form (tile_sweep)")
     ap.add_argument("--n", type=int, default=0, help="box edge (default 256 for turbulence3d, 1024 for shockvortex2d)")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--tile", type=str, default="", help="bx,by,chunk of the step kernel")

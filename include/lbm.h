@@ -250,9 +250,22 @@ int lbm_batch_set_stream(lbm_batch b, void* hip_stream);
    captured graph. */
 int lbm_batch_set_tile(lbm_batch b, const int tile[3]);
 int lbm_batch_get_tile(lbm_batch b, int tile[3]);
-/* Autotuner: times every compiled shape with several march-chunk lengths over
-   reps launches each and keeps the fastest; *best_ms (may be NULL) gets its
-   time per step.  The timed launches read each box's current populations and
+/* Launch form of the batched step: 0 (default) one work-group per tile; 1 a
+   fixed grid of work-groups sized by the kernel's occupancy on the device
+   (a few per compute unit), in which each XCD takes one contiguous eighth
+   of the tiles and its work-groups loop over them (no work-group waits for
+   another).  Both compute the same result to the last bit.  The fixed grid
+   exists for tiles of at most 256 work-items: LBM_EINVAL for on = 1 with a
+   larger tile (and from lbm_batch_set_tile for such a tile while on = 1),
+   and for another value of on.  A batch whose tiles all fit on the device
+   at once launches one work-group per tile either way.  Drops a captured
+   graph. */
+int lbm_batch_set_persistent(lbm_batch b, int on);
+/* The launch form in use (0 or 1), -1 for a NULL batch. */
+int lbm_batch_get_persistent(lbm_batch b);
+/* Autotuner: times every compiled shape with several march-chunk lengths, in
+   both launch forms, over reps launches each and keeps the fastest; *best_ms
+   (may be NULL) gets its time per step.  The timed launches read each box's current populations and
    write the other buffer only, so the states are unchanged.  Synchronous. */
 int lbm_batch_tune(lbm_batch b, int reps, double* best_ms);
 /* Advances every box by n >= 0 steps.  graph_steps > 0: the launches of

@@ -9,6 +9,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "lbm.h"
@@ -789,11 +790,26 @@ int lbm_batch_set_tile(lbm_batch b, const int tile[3]) {
   const lbm::Tile t{tile[0], b->lattice == LBM_D2Q9 && tile[1] == 0 ? 1 : tile[1], tile[2] < 0 ? -1 : tile[2]};
   if (t.chunk < 0 || !lbm::tile_supported(b->lattice, b->precision, {t.bx, t.by, t.chunk > 0 ? t.chunk : 1}))
     return fail(LBM_EINVAL, "lbm_batch_set_tile: launch tile not available");
+  if (b->persistent && !lbm::persistent_supported(t))
+    return fail(LBM_EINVAL, "lbm_batch_set_tile: the persistent launch form needs a tile of at most 256 work-items");
   int rc = batch_select_device(b);
   if (rc != LBM_OK) return rc;
   b->tile = t;
   return batch_layout(b);
 }
+
+int lbm_batch_set_persistent(lbm_batch b, int on) {
+  if (!b) return fail(LBM_EINVAL, "lbm_batch_set_persistent: NULL batch");
+  if (on != 0 && on != 1) return fail(LBM_EINVAL, "lbm_batch_set_persistent: on must be 0 or 1");
+  if (on == 1 && !lbm::persistent_supported(b->tile))
+    return fail(LBM_EINVAL, "lbm_batch_set_persistent: the current tile has more than 256 work-items");
+  int rc = batch_select_device(b);
+  if (rc != LBM_OK) return rc;
+  b->persistent = on == 1;
+  return batch_layout(b);  // drops a captured graph
+}
+
+int lbm_batch_get_persistent(lbm_batch b) { return b ? (b->persistent ? 1 : 0) : -1; }
 
 int lbm_batch_get_tile(lbm_batch b, int tile[3]) {
   if (!b || !tile) return fail(LBM_EINVAL, "lbm_batch_get_tile: NULL argument");
@@ -820,10 +836,18 @@ int lbm_batch_tune(lbm_batch b, int reps, double* best_ms) {
   // Every timed launch reads each box's current buffer and writes the other
   // one (flip 0, no toggle), so the states are left as they were.
   lbm::Tile best = b->tile;
+  bool best_persistent = b->persistent;
   float best_t = -1.0f;
-  for (const lbm::Tile& cand : batch_candidates(b->lattice)) {
-    if (!lbm::tile_supported(b->lattice, b->precision, cand)) continue;
-    b->tile = cand;
+  // every candidate tile in both launch forms
+  std::vector<std::pair<lbm::Tile, bool>> cands;
+  for (const lbm::Tile& t : batch_candidates(b->lattice))
+    if (lbm::tile_supported(b->lattice, b->precision, t)) {
+      cands.push_back({t, false});
+      if (lbm::persistent_supported(t)) cands.push_back({t, true});
+    }
+  for (const auto& cand : cands) {
+    b->tile = cand.first;
+    b->persistent = cand.second;
     if ((rc = batch_layout(b)) != LBM_OK) break;
     if ((e = lbm::launch_batch_step(*b, b->user_stream, 0)) != hipSuccess) break;
     if ((e = hipEventRecord(t0, b->user_stream)) != hipSuccess) break;
@@ -834,12 +858,14 @@ int lbm_batch_tune(lbm_batch b, int reps, double* best_ms) {
     if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
     if (best_t < 0.0f || ms < best_t) {
       best_t = ms;
-      best = cand;
+      best = cand.first;
+      best_persistent = cand.second;
     }
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   b->tile = best;
+  b->persistent = best_persistent;
   const int rc2 = batch_layout(b);
   if (rc != LBM_OK) return rc;
   if (e != hipSuccess) return hip_fail(e, "lbm_batch_tune");

@@ -106,6 +106,7 @@ struct Batch {
   std::vector<int> cur_dev;        // cur of each box as the device table holds it
   int total_blocks = 0;
   Tile tile{};                     // bx, by shared by all boxes; chunk 0 = per-box default
+  bool persistent = false;         // fixed grid looping over the tiles instead of one work-group per tile
   hipStream_t user_stream = nullptr;
   hipStream_t own_stream = nullptr;  // graph replays run here
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -149,6 +150,8 @@ hipError_t launch_toggle(const Batch& b, hipStream_t s);
 Tile default_tile(int D, int precision, const int64_t n[3], bool caloric = false);
 int default_chunk(int D, const int64_t n[3], int bx, int by);
 bool tile_supported(int D, int precision, const Tile& t, bool caloric = false);
+// Whether the persistent form of the batched launch exists for a tile.
+bool persistent_supported(const Tile& t);
 
 }  // namespace lbm
 

@@ -262,7 +262,7 @@ __device__ inline NodeMoments<R> pattern_pulled(const __amdgpu_buffer_rsrc_t* rs
 // PAT: the access-pattern reference (same loads, stores, LDS exchange and
 // barriers, no collision: the streamed populations are stored).
 template <int D, bool DEV, typename S, int BX, int BY, bool CAL = false, bool PAT = false>
-__device__ inline void step_tile(const S* __restrict__ src, S* __restrict__ dst, const StepParams& p, int lb) {
+__device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restrict__ dst, const StepParams& p, int lb) {
   using R = typename StoreOf<S>::R;
   constexpr int Q = lat_q(D);
   constexpr int NHALO = (D == 3) ? 2 * BX + 2 * BY : 2;
@@ -541,6 +541,31 @@ __global__ void __launch_bounds__(BX* BY) batch_step_kernel(const BoxEntry* __re
   const int par = e.cur ^ flip;
   step_tile<D, DEV, S, BX, BY>(static_cast<const S*>(e.buf[par]), static_cast<S*>(e.buf[par ^ 1]), e.p,
                                g - e.block_start);
+}
+
+// The same step with a fixed grid (a few work-groups per compute unit, sized
+// by occupancy): each XCD owns one contiguous eighth of the logical tiles
+// (neighbouring tiles share its L2) and its work-groups take that range's
+// tiles in turn, tile rank, rank + (work-groups per XCD), ...  Every
+// work-group leaves the loop when its range is done; no work-group waits
+// for another.  gridDim.x is a multiple of 8.
+template <int D, bool DEV, typename S, int BX, int BY>
+__global__ void __launch_bounds__(BX* BY) batch_persistent_kernel(const BoxEntry* __restrict__ table, int nboxes,
+                                                                  int total_blocks, int flip) {
+  const int per_xcd = gridDim.x >> 3, xcd = blockIdx.x & 7, rank = blockIdx.x >> 3;
+  const int lo = (int)((long long)total_blocks * xcd / 8), hi = (int)((long long)total_blocks * (xcd + 1) / 8);
+  for (int g = lo + rank; g < hi; g += per_xcd) {
+    int a = 0, z = nboxes - 1;
+    while (a < z) {
+      const int mid = (a + z + 1) >> 1;
+      if (table[mid].block_start <= g) a = mid;
+      else z = mid - 1;
+    }
+    const BoxEntry& e = table[a];
+    const int par = e.cur ^ flip;
+    step_tile<D, DEV, S, BX, BY>(static_cast<const S*>(e.buf[par]), static_cast<S*>(e.buf[par ^ 1]), e.p,
+                                 g - e.block_start);
+  }
 }
 
 // After an odd number of batched steps every box's current buffer changes.
@@ -1022,8 +1047,43 @@ hipError_t launch_step(const Ctx& c, const void* src, void* dst) {
   return dispatch_tile<2, true, float>(c, src, dst);
 }
 
+// Work-groups of the persistent batched launch: the occupancy of the kernel
+// times the compute units, rounded down to a multiple of 8 (the XCDs).  0
+// (one work-group per tile instead) when that covers every tile: rounding a
+// grid near the tile count down would leave a few work-groups two tiles.
+template <int D, bool DEV, typename S, int BX, int BY>
+static hipError_t persistent_grid(const Batch& b, int* grid) {
+  int per_cu = 0, cus = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_persistent_kernel<D, DEV, S, BX, BY>,
+                                                              BX * BY, 0);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b.device);
+  if (e != hipSuccess) return e;
+  const int g = (per_cu * cus / 8) * 8;
+  *grid = per_cu * cus < b.total_blocks && g >= 8 ? g : 0;
+  return hipSuccess;
+}
+
+bool persistent_supported(const Tile& t) { return t.bx * t.by <= 256; }
+
 template <int D, bool DEV, typename S, int BX, int BY>
 static hipError_t launch_batch_t(const Batch& b, hipStream_t s, int flip) {
+  // The looped tile body of a 512-work-item tile does not fit the register
+  // file without a stack frame, so that form exists for tiles of at most 256
+  // work-items only (the host refuses the combination).
+  if constexpr (BX * BY <= 256) {
+    if (b.persistent) {
+      int grid = 0;
+      const hipError_t e = persistent_grid<D, DEV, S, BX, BY>(b, &grid);
+      if (e != hipSuccess) return e;
+      if (grid > 0) {
+        hipLaunchKernelGGL((batch_persistent_kernel<D, DEV, S, BX, BY>), dim3(grid), dim3(BX * BY), 0, s, b.table,
+                           (int)b.boxes.size(), b.total_blocks, flip);
+        return hipGetLastError();
+      }
+    }
+  } else {
+    if (b.persistent) return hipErrorInvalidValue;
+  }
   hipLaunchKernelGGL((batch_step_kernel<D, DEV, S, BX, BY>), dim3(b.total_blocks), dim3(BX * BY), 0, s, b.table,
                      (int)b.boxes.size(), b.total_blocks, flip);
   return hipGetLastError();

@@ -113,10 +113,13 @@ def _load():
     L.lbm_pattern_reference.argtypes = [vp, i64]
     L.lbm_batch_tune.argtypes = [vp, C.c_int, dp]
     L.lbm_batch_step.argtypes = [vp, i64, C.c_int]
+    L.lbm_batch_set_persistent.argtypes = [vp, C.c_int]
+    L.lbm_batch_get_persistent.argtypes = [vp]
     for name in ("lbm_create", "lbm_destroy", "lbm_set_stream", "lbm_init_fields", "lbm_step", "lbm_moments",
                  "lbm_diagnostics", "lbm_diagnostics_noalloc", "lbm_get_state", "lbm_set_state", "lbm_device_copy", "lbm_batch_create",
                  "lbm_batch_destroy", "lbm_batch_set_stream", "lbm_batch_set_tile", "lbm_batch_get_tile",
-                 "lbm_get_tile", "lbm_get_dims", "lbm_pattern_reference", "lbm_batch_tune", "lbm_batch_step", "lbm_fields_add", "lbm_filter_moments", "lbm_nn_create",
+                 "lbm_get_tile", "lbm_get_dims", "lbm_pattern_reference", "lbm_batch_tune",
+                 "lbm_batch_set_persistent", "lbm_batch_get_persistent", "lbm_batch_step", "lbm_fields_add", "lbm_filter_moments", "lbm_nn_create",
                  "lbm_nn_destroy", "lbm_nn_set_stream", "lbm_nn_set_params", "lbm_nn_get_params", "lbm_nn_get_grads",
                  "lbm_nn_zero_grad", "lbm_nn_set_scaling", "lbm_nn_forward", "lbm_nn_loss_backward",
                  "lbm_nn_adam_step", "lbm_nn_take_loss", "lbm_nn_correct", "lbm_nn_fields_to_planes", "lbm_fields_set",
@@ -388,6 +391,14 @@ def lbm_batch_tune(b, reps: int = 5) -> float:
     ms = C.c_double()
     _check(_L.lbm_batch_tune(b, int(reps), C.byref(ms)))
     return ms.value
+
+
+def lbm_batch_set_persistent(b, on: bool) -> int:
+    return _check(_L.lbm_batch_set_persistent(b, 1 if on else 0))
+
+
+def lbm_batch_get_persistent(b) -> bool:
+    return _L.lbm_batch_get_persistent(b) == 1
 
 
 def lbm_batch_step(b, n: int = 1, graph_steps: int = 0) -> int:

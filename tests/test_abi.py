@@ -114,6 +114,8 @@ def test_batch_null_arguments_fail_cleanly(lbm):
     assert L.lbm_batch_step(None, 1, 0) == lbm.LBM_EINVAL
     assert L.lbm_batch_tune(None, 1, None) == lbm.LBM_EINVAL
     assert L.lbm_batch_set_stream(None, None) == lbm.LBM_EINVAL
+    assert L.lbm_batch_set_persistent(None, 1) == lbm.LBM_EINVAL
+    assert L.lbm_batch_get_persistent(None) == -1
 
 
 @pytest.mark.parametrize("channels,dims,needle", [

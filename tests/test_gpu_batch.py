@@ -80,6 +80,47 @@ def test_batch_equals_individual_steps(fp32):
             lbm.lbm_destroy(h)
 
 
+@pytest.mark.parametrize("fp32", [True, False])
+def test_persistent_launch_equals_individual_steps(fp32):
+    """The fixed-grid launch form, on a batch of more tiles than the device
+    holds at once (64 x 1 tiles with 4-row chunks over three ragged boxes of
+    up to a million nodes: 10,976 tiles), so that work-groups loop over
+    several tiles each: every box ends bit for bit where lbm_step takes it
+    with the same tile, also across graph replays."""
+    lbm = _lbm()
+    prec = lbm.LBM_FP32_DEV if fp32 else lbm.LBM_FP64
+    dims = [(1024, 1024), (960, 1088), (1000, 700)]
+    boxes = []
+    for k, (nx, ny) in enumerate(dims):
+        rho, u, T = I.turbulence_box2d(nx, ny, seed=80 + k, Ma_t=0.3, T0=0.15)
+        boxes.append(dict(dims=(nx, ny), fields=(rho, u, T), mu=I.taylor_viscosity(u[:, 0])))
+    tile = (64, 1, 4)
+    print(f"[gpu case] persistent batch {dims} tile {tile} fp32={fp32}", flush=True)
+    hs = []
+    for lst_tile in (tile, None):
+        for b in boxes:
+            h = lbm.lbm_create(2, b["dims"], 1.4, 0.7, b["mu"], precision=prec, visc_exponent=0.76, T_ref=0.15,
+                               tile=lst_tile)
+            lbm.lbm_set_stream(h, torch.cuda.current_stream())
+            lbm.lbm_init_fields(h, *(torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in b["fields"]))
+            hs.append(h)
+    ref, bat = hs[:3], hs[3:]
+    b = lbm.lbm_batch_create(bat)
+    try:
+        lbm.lbm_batch_set_tile(b, tile)
+        lbm.lbm_batch_set_persistent(b, True)
+        assert lbm.lbm_batch_get_persistent(b) and lbm.lbm_batch_get_tile(b) == tile
+        lbm.lbm_batch_step(b, 5)
+        lbm.lbm_batch_step(b, 12, 4)
+        for h in ref:
+            lbm.lbm_step(h, 17)
+        assert _same(_states(lbm, ref, fp32), _states(lbm, bat, fp32))
+    finally:
+        lbm.lbm_batch_destroy(b)
+        for h in hs:
+            lbm.lbm_destroy(h)
+
+
 def test_batch_graph_replays_interleaved_with_other_work():
     """Graph replays (even and odd captured lengths, remainders launched
     directly), with diagnostics, a single-box step and host synchronisation
@@ -155,9 +196,53 @@ def test_batch_d3q27_uneven_boxes():
         for h in hs_ref:
             lbm.lbm_step(h, 11)
         assert _same(_states(lbm, hs_ref, True), _states(lbm, hs_bat, True))
+        print("[gpu case] D3Q27 batch, launch form switches", flush=True)
+        lbm.lbm_batch_set_tile(b, (64, 8, 0))
+        with pytest.raises(lbm.LbmError) as e:  # the fixed grid needs <= 256 work-items per tile
+            lbm.lbm_batch_set_persistent(b, True)
+        assert e.value.code == lbm.LBM_EINVAL
+        lbm.lbm_batch_set_tile(b, (32, 8, 0))
+        lbm.lbm_batch_set_persistent(b, True)
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_batch_set_tile(b, (64, 8, 0))
+        assert e.value.code == lbm.LBM_EINVAL
+        assert lbm.lbm_batch_get_tile(b)[:2] == (32, 8) and lbm.lbm_batch_get_persistent(b)
     finally:
         lbm.lbm_batch_destroy(b)
         for h in hs_ref + hs_bat:
+            lbm.lbm_destroy(h)
+
+
+@pytest.mark.parametrize("fp32,tile", [(True, (32, 8, 2)), (False, (64, 4, 2))])
+def test_persistent_launch_d3q27(fp32, tile):
+    """The fixed-grid form of the D3Q27 batch on about a thousand tiles (the
+    device holds a few hundred 256-work-item work-groups of this kernel at
+    once): bit for bit where lbm_step takes each box with the same tile."""
+    lbm = _lbm()
+    prec = lbm.LBM_FP32_DEV if fp32 else lbm.LBM_FP64
+    dims = [(64, 64, 40), (48, 72, 36), (40, 40, 64)]
+    print(f"[gpu case] D3Q27 persistent batch {dims} tile {tile} fp32={fp32}", flush=True)
+    hs = []
+    for t in (tile, tile):
+        for k, d in enumerate(dims):
+            f = I.smooth_random(3, d, seed=90 + k, u_amp=0.05)
+            h = lbm.lbm_create(3, d, 1.4, 0.7, 0.02, precision=prec, visc_exponent=0.76, T_ref=0.15, tile=t)
+            lbm.lbm_set_stream(h, torch.cuda.current_stream())
+            lbm.lbm_init_fields(h, *f)
+            hs.append(h)
+    ref, bat = hs[:3], hs[3:]
+    b = lbm.lbm_batch_create(bat)
+    try:
+        lbm.lbm_batch_set_tile(b, tile)
+        lbm.lbm_batch_set_persistent(b, True)
+        lbm.lbm_batch_step(b, 3)
+        lbm.lbm_batch_step(b, 6, 3)
+        for h in ref:
+            lbm.lbm_step(h, 9)
+        assert _same(_states(lbm, ref, fp32), _states(lbm, bat, fp32))
+    finally:
+        lbm.lbm_batch_destroy(b)
+        for h in hs:
             lbm.lbm_destroy(h)
 
 
@@ -180,6 +265,7 @@ def test_batch_argument_errors():
             with pytest.raises(lbm.LbmError) as e:
                 lbm.lbm_batch_set_tile(b, (48, 1, 8))
             assert e.value.code == lbm.LBM_EINVAL
+            assert lbm.raw().lbm_batch_set_persistent(b, 2) == lbm.LBM_EINVAL
         finally:
             lbm.lbm_batch_destroy(b)
     finally:
