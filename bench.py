@@ -33,6 +33,10 @@ reported beside it.
 (He-normal weights, normalised random input), --steps timed passes: the
 bf16 matrix-core roofline of the convolution kernels, for profiling.
 
+--workload nntrain64: training samples of the same network at 64^3 (random
+input and target; loss, input and weight gradients, Adam), --steps timed
+samples: the roofline of the backward kernels, for profiling.
+
 One timed step = one lbm_step (one launch of the fused kernel) over the whole
 box; the diagnostics reduction runs every --diag-every steps inside the timed
 region.  Prints one JSON line (metric MLUPS) with the roofline of the step
@@ -458,6 +462,65 @@ def run_nnforward(args, torch, lbm, dev):
     return out
 
 
+def run_nntrain(args, torch, lbm, dev):
+    """Training samples of the corrector network at 64^3 (see the module docstring)."""
+    import numpy as np
+
+    from paper_2102_09512_amd import corrector as Cr
+
+    w = Cr.Workload()
+    nc = w.n_coarse
+    V = nc ** 3
+    ch = w.channels
+    net = lbm.lbm_nn_create(list(ch), (nc, nc, nc))
+    try:
+        lbm.lbm_nn_set_params(net, Cr.initial_params(ch, seed=0, last_gain=1.0))
+        lbm.lbm_nn_set_scaling(net, np.zeros(5), np.ones(5), np.ones(ch[-1]))
+        stream = torch.cuda.current_stream(dev)
+        lbm.lbm_nn_set_stream(net, stream)
+        g = torch.Generator(device="cpu").manual_seed(0)
+        x = torch.randn((5, V), generator=g, dtype=torch.float32).to(dev)
+        y = (x.cpu() + 0.1 * torch.randn((ch[0], V), generator=g, dtype=torch.float32)).to(dev)  # target fields
+
+        def sample(t):
+            lbm.lbm_nn_zero_grad(net)
+            lbm.lbm_nn_loss_backward(net, x, y, sync=False)
+            lbm.lbm_nn_adam_step(net, 1e-4, t=t)
+
+        for t in range(max(args.warmup, 1)):
+            sample(t + 1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for t in range(args.steps):
+            sample(args.warmup + t + 1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        step_s = e0.elapsed_time(e1) / 1e3 / args.steps
+        loss_sum, count = lbm.lbm_nn_take_loss(net)
+    finally:
+        lbm.lbm_nn_destroy(net)
+    # forward, input gradients of layers 1.. (the network input needs none) and weight gradients
+    conv = [2 * 27 * ch[l] * ch[l + 1] * V for l in range(len(ch) - 1)]
+    flops = sum(conv) + sum(conv[1:]) + sum(conv)
+    tflops = flops / step_s / 1e12
+    return {
+        "metric": "TFLOP/s (corrector network training sample: forward, backward, weight gradient, Adam at 64^3)",
+        "value": round(tflops, 2), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16 (fp32 accumulation)", "data": "synthetic (seeded)",
+        "config": {"workload": "corrector network training sample 64^3, channels " + "-".join(map(str, ch)),
+                   "nodes": V, "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(tflops / 2500.0, 5), "traffic": None,
+                     "kernel": "network training sample (conv, backward-data conv, weight-gradient, loss, Adam)",
+                     "avg_sample_ms": round(step_s * 1e3, 4), "algorithmic_flops_per_sample": flops},
+        "mean_loss": loss_sum / max(count, 1),
+    }
+
+
 def cpu_forward_baseline(w):
     """The oracle's FP64 network forward on a 32^3 sample, scaled to forward
     passes of the 64^3 grid per second."""
@@ -481,7 +544,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["turbulence3d", "shockvortex2d", "ensemble2d", "learned64", "nnforward64"],
+    ap.add_argument("--workload", choices=["turbulence3d", "shockvortex2d", "ensemble2d", "learned64", "nnforward64",
+                                               "nntrain64"],
                     default="turbulence3d")
     ap.add_argument("--train-seeds", type=int, default=32, help="learned corrector: training seeds")
     ap.add_argument("--eval-seeds", type=int, default=4, help="learned corrector: held-out seeds")
@@ -525,6 +589,9 @@ def main():
         return
     if args.workload == "nnforward64":
         print(json.dumps(run_nnforward(args, torch, lbm, dev)), flush=True)
+        return
+    if args.workload == "nntrain64":
+        print(json.dumps(run_nntrain(args, torch, lbm, dev)), flush=True)
         return
     n = args.n or (256 if args.workload == "turbulence3d" else 1024)
     _log(f"[bench] generating the {args.workload} input, n = {n}")

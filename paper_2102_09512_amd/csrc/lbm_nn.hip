@@ -177,48 +177,56 @@ __global__ void __launch_bounds__(64 * kW) conv_kernel(const __bf16* __restrict_
   const int tx = g.nx / kTX, ty = g.ny / kTY;
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (b % tx) * kTX, y0 = ((b / tx) % ty) * kTY, z0 = (b / (tx * ty)) * kTZ;
-  stage_tile<CIN>(in, tile, g, x0, y0, z0);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r = lane & 31, half = lane >> 5;
-  float bo[16];  // loaded before the tap loop, whose time covers their latency
+  // Wave w owns the kTY output rows of plane z = w of the tile.  For one
+  // (dz, dx) pair and 16-channel block, each of the kTY + 2 input rows of
+  // the halo column is read from LDS once and feeds the (up to three)
+  // output rows it reaches through the taps dy = -1, 0, 1, each with its own
+  // weights: half the LDS reads of one read per tap and row.  The weights of
+  // group (dz, dx) come from L2 while the group before it computes (two
+  // register sets, one group of matrix-core work ahead); the first group's
+  // and the biases are requested before the tile is staged.
+  static_assert(kR == kTY && kW == kTZ, "a wavefront owns one plane of the tile");
+  constexpr int NC = CIN / 16;
+  bf8 a[2][NC][3];  // [set][16-channel block][dy + 1]
+  auto load_group = [&](int gi, bf8(&dst)[NC][3]) {
+    const int dz = gi / 3 - 1, dx = gi % 3 - 1;
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int t = (dx + 1) + 3 * k + 9 * (dz + 1);
+        dst[cc][k] = *(const bf8*)(wp + ((size_t)(t * NC + cc) * 32 + r) * 16 + 8 * half);
+      }
+  };
+  load_group(0, a[0]);
+  float bo[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int c = 8 * (i >> 2) + 4 * half + (i & 3);
     bo[i] = bias && c < cout ? bias[c] : 0.f;
   }
+  stage_tile<CIN>(in, tile, g, x0, y0, z0);
   f16v acc[kR] = {};
-  // Wave w owns the kTY output rows of plane z = w of the tile.  For one
-  // (dz, dx) pair and 16-channel block, each of the kTY + 2 input rows of
-  // the halo column is read from LDS once and feeds the (up to three)
-  // output rows it reaches through the taps dy = -1, 0, 1, each with its own
-  // weights: half the LDS reads of one read per tap and row.  Fully
-  // unrolled, so the compiler hoists later loads over earlier matrix-core
-  // work.
-  static_assert(kR == kTY && kW == kTZ, "a wavefront owns one plane of the tile");
 #pragma unroll
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int hz = w + dz + 1;
+  for (int gi = 0; gi < 9; ++gi) {
+    if (gi + 1 < 9) load_group(gi + 1, a[(gi + 1) & 1]);
+    __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of this group's work
+    const int dz = gi / 3 - 1, dx = gi % 3 - 1;
+    const int hz = w + dz + 1, hx = r + dx + 1;
+    const __bf16* col = tile + hx * CIN + hz * kHY * kHX * CIN;
 #pragma unroll
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int hx = r + dx + 1;
-      const __bf16* col = tile + hx * CIN + hz * kHY * kHX * CIN;
+    for (int cc = 0; cc < NC; ++cc) {
+      const int off = swizzle<CIN>(2 * cc + half, hx) * 8;
 #pragma unroll
-      for (int cc = 0; cc < CIN / 16; ++cc) {
-        bf8 a[3];  // weights of the taps (dx, dy, dz), dy = -1, 0, 1
+      for (int hy = 0; hy < kTY + 2; ++hy) {
+        const bf8 bv = *(const bf8*)(col + hy * kHX * CIN + off);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          const int t = (dx + 1) + 3 * k + 9 * (dz + 1);
-          a[k] = *(const bf8*)(wp + ((size_t)(t * (CIN / 16) + cc) * 32 + r) * 16 + 8 * half);
-        }
-        const int off = swizzle<CIN>(2 * cc + half, hx) * 8;
-#pragma unroll
-        for (int hy = 0; hy < kTY + 2; ++hy) {
-          const bf8 bv = *(const bf8*)(col + hy * kHX * CIN + off);
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            const int j = hy - k;  // output row reached through dy = k - 1
-            if (j >= 0 && j < kTY) acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[k], bv, acc[j], 0, 0, 0);
-          }
+          const int j = hy - k;  // output row reached through dy = k - 1
+          if (j >= 0 && j < kTY)
+            acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[gi & 1][cc][k], bv, acc[j], 0, 0, 0);
         }
       }
     }
@@ -243,6 +251,18 @@ __global__ void __launch_bounds__(64 * kW) conv_pair_kernel(const __bf16* __rest
   const int tx = g.nx / kTX, ty = g.ny / kTY;
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (b % tx) * kTX, y0 = ((b / tx) % ty) * kTY, z0 = (b / (tx * ty)) * kTZ;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 31, half = lane >> 5;
+  // every weight operand and the biases are requested before the staging
+  bf8 a[14];
+#pragma unroll
+  for (int p = 0; p < 14; ++p) a[p] = *(const bf8*)(wq + ((size_t)p * 32 + r) * 16 + 8 * half);
+  float bo[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int c = 8 * (i >> 2) + 4 * half + (i & 3);
+    bo[i] = bias && c < cout ? bias[c] : 0.f;
+  }
   {
     constexpr int NIT = (NN + 64 * kW - 1) / (64 * kW);
     bf8 stage[NIT];
@@ -262,18 +282,9 @@ __global__ void __launch_bounds__(64 * kW) conv_pair_kernel(const __bf16* __rest
     }
     __syncthreads();
   }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int r = lane & 31, half = lane >> 5;
-  float bo[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int c = 8 * (i >> 2) + 4 * half + (i & 3);
-    bo[i] = bias && c < cout ? bias[c] : 0.f;
-  }
   f16v acc[kR] = {};
 #pragma unroll
   for (int p = 0; p < 14; ++p) {
-    const bf8 a = *(const bf8*)(wq + ((size_t)p * 32 + r) * 16 + 8 * half);
     const int t = min(2 * p + half, 26);
     const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
     const __bf16* col = tile + (r + dx + 1) * 8;
@@ -281,7 +292,7 @@ __global__ void __launch_bounds__(64 * kW) conv_pair_kernel(const __bf16* __rest
     for (int j = 0; j < kR; ++j) {
       const int q = w * kR + j, hy = q % kTY + dy + 1, hz = q / kTY + dz + 1;
       const bf8 bv = *(const bf8*)(col + (hz * kHY + hy) * kHX * 8);
-      acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[j], 0, 0, 0);
+      acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[p], bv, acc[j], 0, 0, 0);
     }
   }
   conv_epilogue<false>(acc, bo, relu, nullptr, out, cout, g, V, x0, y0, z0, w, r, half);
@@ -303,35 +314,42 @@ __global__ void __launch_bounds__(64 * kW) conv_narrow_kernel(const __bf16* __re
   const int tx = g.nx / kTX, ty = g.ny / kTY;
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (b % tx) * kTX, y0 = ((b / tx) % ty) * kTY, z0 = (b / (tx * ty)) * kTZ;
-  stage_tile<32>(in, tile, g, x0, y0, z0);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int n16 = lane & 15, grp = lane >> 4;
+  // weights of group (dz, dx), taps dy = -1, 0, 1: A[o = l%16][i = 8(l/16) + j];
+  // one group ahead, as in conv_kernel
+  bf8 a[2][3];
+  auto load_group = [&](int gi, bf8(&dst)[3]) {
+    const int dz = gi / 3 - 1, dx = gi % 3 - 1;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int t = (dx + 1) + 3 * k + 9 * (dz + 1);
+      dst[k] = *(const bf8*)(wn + ((size_t)t * 16 + n16) * 32 + 8 * grp);
+    }
+  };
+  load_group(0, a[0]);
   float bo[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) bo[v] = bias && 4 * grp + v < cout ? bias[4 * grp + v] : 0.f;
+  stage_tile<32>(in, tile, g, x0, y0, z0);
   f4v acc[kTY][2] = {};
 #pragma unroll
-  for (int dz = -1; dz <= 1; ++dz) {
+  for (int gi = 0; gi < 9; ++gi) {
+    if (gi + 1 < 9) load_group(gi + 1, a[(gi + 1) & 1]);
+    __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of this group's work
+    const int dz = gi / 3 - 1, dx = gi % 3 - 1;
     const int hz = w + dz + 1;
 #pragma unroll
-    for (int dx = -1; dx <= 1; ++dx) {
-      bf8 a[3];  // taps (dx, dy, dz), dy = -1, 0, 1: A[o = l%16][i = 8(l/16) + j]
+    for (int hy = 0; hy < kTY + 2; ++hy) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int t = (dx + 1) + 3 * k + 9 * (dz + 1);
-        a[k] = *(const bf8*)(wn + ((size_t)t * 16 + n16) * 32 + 8 * grp);
-      }
+      for (int h = 0; h < 2; ++h) {
+        const int hx = 16 * h + n16 + dx + 1;
+        const bf8 bv = *(const bf8*)(tile + ((hz * kHY + hy) * kHX + hx) * 32 + swizzle<32>(grp, hx) * 8);
 #pragma unroll
-      for (int hy = 0; hy < kTY + 2; ++hy) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int hx = 16 * h + n16 + dx + 1;
-          const bf8 bv = *(const bf8*)(tile + ((hz * kHY + hy) * kHX + hx) * 32 + swizzle<32>(grp, hx) * 8);
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            const int j = hy - k;
-            if (j >= 0 && j < kTY) acc[j][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[k], bv, acc[j][h], 0, 0, 0);
-          }
+        for (int k = 0; k < 3; ++k) {
+          const int j = hy - k;
+          if (j >= 0 && j < kTY)
+            acc[j][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[gi & 1][k], bv, acc[j][h], 0, 0, 0);
         }
       }
     }
