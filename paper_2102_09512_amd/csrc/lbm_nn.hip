@@ -376,8 +376,9 @@ __global__ void __launch_bounds__(64 * kW) conv_narrow_kernel(const __bf16* __re
 // staged in LDS channel-major, so that the node index runs along the
 // matrix-core K dimension: lane (r, h) reads 8 consecutive nodes of channel r
 // as one 16-byte word.  The x offset of a tap is 0, 1 or 2 elements inside
-// two aligned words and is taken out with funnel shifts.  Wave w owns slots
-// w, w + 4, ..., w + 24 and keeps their sums in registers across the tiles.
+// two aligned words and is taken out with funnel shifts.  Wave w owns seven
+// slots (the three dx taps of two (dy, dz) pairs and one more; see the loop)
+// and keeps their sums in registers across the tiles.
 constexpr int kGX = 32, kGY = 4, kGZ = 2;
 constexpr int kGHY = kGY + 2, kGHZ = kGZ + 2, kGHX = kGX + 2;
 constexpr int kGRow = 40;                           // halo row: 34 nodes, padded to a 16-byte multiple
@@ -425,6 +426,11 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const __bf16* __restrict__ i
       for (int j = 0; j < 8; ++j) dst[j * kGPlaneD] = val[j];
     }
     __syncthreads();
+    // The three slots of one (dy, dz) pair (dx = -1, 0, 1) read the same two
+    // words of a channel row and differ by a shift of 0, 1 or 2 elements, so a
+    // wave owns whole pairs: wave w takes the pairs 2w and 2w + 1 (slots 6w ..
+    // 6w + 5) and a seventh slot, dx = w - 1 of pair 8 (slot 24 + w) for w < 3
+    // and the bias (slot 27) for w = 3.  Two LDS reads serve three products.
 #pragma unroll 1
     for (int row = 0; row < kGY * kGZ; ++row) {
       const int yy = row % kGY, zz = row / kGY;
@@ -432,37 +438,46 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const __bf16* __restrict__ i
       for (int kb = 0; kb < kGX; kb += 16) {
         // the output gradient of these 16 nodes serves all seven slots of the wave
         const bf8 b = *(const bf8*)(dT + r * kGPlaneD + (zz * kGY + yy) * kGX + kb + 8 * half);
-#pragma unroll
-        for (int k = 0; k < 7; ++k) {
-          const int t = w + 4 * k;  // 0..27: every slot exactly once over the four waves
-          const int o = t % 3, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;  // o = dx + 1
-          bf8 a;
-          if (t == 27) {
-            a = ones;
-          } else if (r < CIN) {
-            const __bf16* src = inT + r * kGPlaneIn + ((zz + dz + 1) * kGHY + yy + dy + 1) * kGRow + kb + 8 * half;
-            const u4 lo = *(const u4*)src, hi = *(const u4*)(src + 8);
-            u4 v;
-            if (o == 0) {
-              v = lo;
-            } else if (o == 2) {
-              v = u4{lo.y, lo.z, lo.w, hi.x};
-            } else {
-              v = u4{__builtin_amdgcn_alignbit(lo.y, lo.x, 16), __builtin_amdgcn_alignbit(lo.z, lo.y, 16),
-                     __builtin_amdgcn_alignbit(lo.w, lo.z, 16), __builtin_amdgcn_alignbit(hi.x, lo.w, 16)};
-            }
-            a = __builtin_bit_cast(bf8, v);
+        auto words = [&](int pair, u4& lo, u4& hi) {
+          const int dy = pair % 3 - 1, dz = pair / 3 - 1;
+          const __bf16* src = inT + r * kGPlaneIn + ((zz + dz + 1) * kGHY + yy + dy + 1) * kGRow + kb + 8 * half;
+          lo = *(const u4*)src;
+          hi = *(const u4*)(src + 8);
+        };
+        auto shifted = [&](const u4& lo, const u4& hi, int o) {  // the 8 elements from element o of lo
+          u4 v;
+          if (o == 0) {
+            v = lo;
+          } else if (o == 2) {
+            v = u4{lo.y, lo.z, lo.w, hi.x};
           } else {
-            a = bf8{};
+            v = u4{__builtin_amdgcn_alignbit(lo.y, lo.x, 16), __builtin_amdgcn_alignbit(lo.z, lo.y, 16),
+                   __builtin_amdgcn_alignbit(lo.w, lo.z, 16), __builtin_amdgcn_alignbit(hi.x, lo.w, 16)};
           }
-          acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[k], 0, 0, 0);
+          return __builtin_bit_cast(bf8, v);
+        };
+#pragma unroll
+        for (int gp = 0; gp < 2; ++gp) {
+          u4 lo{}, hi{};
+          if (r < CIN) words(2 * w + gp, lo, hi);
+#pragma unroll
+          for (int o = 0; o < 3; ++o)
+            acc[3 * gp + o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(shifted(lo, hi, o), b, acc[3 * gp + o], 0, 0, 0);
         }
+        bf8 a = ones;
+        if (w < 3) {
+          u4 lo{}, hi{};
+          if (r < CIN) words(8, lo, hi);
+          a = shifted(lo, hi, w);
+        }
+        acc[6] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[6], 0, 0, 0);
       }
     }
   }
 #pragma unroll
   for (int k = 0; k < 7; ++k) {
-    float* dst = part + ((size_t)(w + 4 * k) * gridDim.x + bl) * 1024;
+    const int t = k < 6 ? 6 * w + k : (w < 3 ? 24 + w : 27);
+    float* dst = part + ((size_t)t * gridDim.x + bl) * 1024;
 #pragma unroll
     for (int i = 0; i < 16; ++i) dst[(8 * (i >> 2) + 4 * half + (i & 3)) * 32 + r] = acc[k][i];
   }
