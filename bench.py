@@ -77,6 +77,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def nn_source_hash() -> str:
+    """Hash of the network kernels' source (profiles name the one they measured)."""
+    with open(os.path.join(ROOT, "paper_2102_09512_amd", "csrc", "lbm_nn.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
 def measured_traffic(workload: str, precision: str, tile):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the current kernel source with the same launch tile."""
@@ -456,6 +462,7 @@ def run_nnforward(args, torch, lbm, dev):
                      "frac": round(tflops / 2500.0, 5), "traffic": None,
                      "kernel": "network forward (4 conv launches + input packing)",
                      "avg_forward_ms": round(fwd_s * 1e3, 4), "algorithmic_flops_per_forward": flops},
+        "kernel_source": nn_source_hash(),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_forward_baseline(w)
@@ -518,6 +525,7 @@ def run_nntrain(args, torch, lbm, dev):
                      "kernel": "network training sample (conv, backward-data conv, weight-gradient, loss, Adam)",
                      "avg_sample_ms": round(step_s * 1e3, 4), "algorithmic_flops_per_sample": flops},
         "mean_loss": loss_sum / max(count, 1),
+        "kernel_source": nn_source_hash(),
     }
 
 

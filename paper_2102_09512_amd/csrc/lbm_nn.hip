@@ -367,7 +367,8 @@ __global__ void __launch_bounds__(64 * kW) conv_narrow_kernel(const __bf16* __re
     }
 }
 
-// Weight and bias gradients of one layer, per work-group partial sums:
+// Weight and bias gradients of one layer, per work-group partial sums over
+// the layer's real channels (i < cin, o < cout):
 //   slot t < 27: part[t][b][i][o] = sum over the group's nodes v of in[v + s_t][i] dout[v][o]
 //   slot 27:     part[27][b][i][o] = sum over the group's nodes v of dout[v][o] (every row i)
 // (the bias gradient as the product with a row of ones).  Work-group b takes
@@ -391,7 +392,8 @@ typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 template <int CIN>
 __global__ void __launch_bounds__(256) wgrad_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ dout,
-                                                    float* __restrict__ part, const Grid g, int ntiles, int tpb) {
+                                                    float* __restrict__ part, const Grid g, int ntiles, int tpb,
+                                                    int cin, int cout) {
   __shared__ __attribute__((aligned(16))) __bf16 inT[CIN * kGPlaneIn];
   __shared__ __attribute__((aligned(16))) __bf16 dT[32 * kGPlaneD];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -474,38 +476,58 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const __bf16* __restrict__ i
       }
     }
   }
+  // accumulator i of lane l holds input channel m = 8(i/4) + 4(l/32) + i%4
+  // and output channel r = l%32
 #pragma unroll
   for (int k = 0; k < 7; ++k) {
     const int t = k < 6 ? 6 * w + k : (w < 3 ? 24 + w : 27);
-    float* dst = part + ((size_t)t * gridDim.x + bl) * 1024;
+    float* dst = part + ((size_t)t * gridDim.x + bl) * cin * cout;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) dst[(8 * (i >> 2) + 4 * half + (i & 3)) * 32 + r] = acc[k][i];
+    for (int i = 0; i < 16; ++i) {
+      const int m = 8 * (i >> 2) + 4 * half + (i & 3);
+      if (m < cin && r < cout) dst[m * cout + r] = acc[k][i];
+    }
   }
 }
 
-// First stage of the gradient sum: part2[t][s][i][o] = sum of part[t][b][i][o]
-// over the s-th of nseg equal runs of b (blockIdx.y = s); fixed order.
-__global__ void __launch_bounds__(256) wgrad_partial_sum_kernel(const float* __restrict__ part, int nblk, int nseg,
-                                                                float* __restrict__ part2) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= 28 * 1024) return;
-  const int t = e / 1024, io = e % 1024, sgm = blockIdx.y;
-  const int b0 = (int)((long long)nblk * sgm / nseg), b1 = (int)((long long)nblk * (sgm + 1) / nseg);
+// src[0] + src[stride] + ... + src[(n - 1) stride], added in that order, with
+// eight loads in flight at a time.
+__device__ inline float ordered_sum(const float* __restrict__ src, size_t stride, int n) {
   float acc = 0.f;
-  for (int b = b0; b < b1; ++b) acc += part[((size_t)t * nblk + b) * 1024 + io];
-  part2[((size_t)t * nseg + sgm) * 1024 + io] = acc;
+  int b = 0;
+  for (; b + 8 <= n; b += 8) {
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = src[(size_t)(b + j) * stride];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc += v[j];
+  }
+  for (; b < n; ++b) acc += src[(size_t)b * stride];
+  return acc;
 }
 
-// grad[t][i][o] += sum_b part[t][b][i][o] (t < 27, i < cin, o < cout) and
-// grad_b[o] += sum_b part[27][b][0][o]; fixed summation order
+// First stage of the gradient sum: part2[t][s][io] = sum of part[t][b][io]
+// over the s-th of nseg equal runs of b (blockIdx.y = s), io < cio = cin
+// cout; fixed order.
+__global__ void __launch_bounds__(256) wgrad_partial_sum_kernel(const float* __restrict__ part, int nblk, int nseg,
+                                                                int cio, float* __restrict__ part2) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 28 * cio) return;
+  const int t = e / cio, io = e % cio, sgm = blockIdx.y;
+  const int b0 = (int)((long long)nblk * sgm / nseg), b1 = (int)((long long)nblk * (sgm + 1) / nseg);
+  part2[((size_t)t * nseg + sgm) * cio + io] = ordered_sum(part + ((size_t)t * nblk + b0) * cio + io, cio, b1 - b0);
+}
+
+// grad[t][i][o] += sum_b part[t][b][i][o] (t < 27) and grad_b[o] += sum_b
+// part[27][b][0][o], part laid out [28][nblk][cin][cout]; fixed summation order
 __global__ void __launch_bounds__(256) wgrad_reduce_kernel(const float* __restrict__ part, int nblk, int cin, int cout,
                                                            float* __restrict__ grad, float* __restrict__ grad_b) {
+  const int cio = cin * cout;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= 28 * 1024) return;
-  const int t = e / 1024, i = (e / 32) % 32, o = e % 32;
-  if (o >= cout || (t < 27 && i >= cin) || (t == 27 && i != 0)) return;
-  float s = 0.f;
-  for (int b = 0; b < nblk; ++b) s += part[((size_t)t * nblk + b) * 1024 + i * 32 + o];
+  if (e >= 28 * cio) return;
+  const int t = e / cio, io = e % cio, i = io / cout, o = io % cout;
+  if (t == 27 && i != 0) return;
+  const float s = ordered_sum(part + (size_t)t * nblk * cio + io, cio, nblk);
   if (t < 27) grad[((size_t)t * cin + i) * cout + o] += s;
   else grad_b[o] += s;
 }
@@ -991,16 +1013,17 @@ int lbm_nn_loss_backward(lbm_nn n, const float* x, const float* target, double* 
     const Layer& ly = n->layers[l];
     if (ly.cinp == 16)
       hipLaunchKernelGGL((lbmnn::wgrad_kernel<16>), dim3(nblk), dim3(256), 0, n->stream, n->act[l], dcur, n->part, n->g,
-                         ntiles, tpb);
+                         ntiles, tpb, ly.cin, ly.cout);
     else
       hipLaunchKernelGGL((lbmnn::wgrad_kernel<32>), dim3(nblk), dim3(256), 0, n->stream, n->act[l], dcur, n->part, n->g,
-                         ntiles, tpb);
+                         ntiles, tpb, ly.cin, ly.cout);
     NN_HIP(hipGetLastError(), "weight gradient kernel");
     const int nseg = nblk < lbmnn::kGSegments ? nblk : lbmnn::kGSegments;
-    hipLaunchKernelGGL(lbmnn::wgrad_partial_sum_kernel, dim3(28 * 1024 / 256, nseg), dim3(256), 0, n->stream,
-                       n->part, nblk, nseg, n->part2);
+    const int cio = ly.cin * ly.cout, sum_blocks = (28 * cio + 255) / 256;
+    hipLaunchKernelGGL(lbmnn::wgrad_partial_sum_kernel, dim3(sum_blocks, nseg), dim3(256), 0, n->stream, n->part,
+                       nblk, nseg, cio, n->part2);
     NN_HIP(hipGetLastError(), "weight gradient partial sums");
-    hipLaunchKernelGGL(lbmnn::wgrad_reduce_kernel, dim3(28 * 1024 / 256), dim3(256), 0, n->stream, n->part2, nseg,
+    hipLaunchKernelGGL(lbmnn::wgrad_reduce_kernel, dim3(sum_blocks), dim3(256), 0, n->stream, n->part2, nseg,
                        ly.cin, ly.cout, n->grads + ly.w_off, n->grads + ly.b_off);
     NN_HIP(hipGetLastError(), "weight gradient reduction");
     if (l > 0) {
