@@ -564,6 +564,8 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="box edge (default 256 for turbulence3d, 1024 for shockvortex2d)")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--tile", type=str, default="", help="bx,by,chunk of the step kernel")
+    ap.add_argument("--layout", choices=["rows", "blocks"], default="rows",
+                    help="device layout of the populations (lbm_options.layout): slot rows or 64-node blocks")
     ap.add_argument("--deriv", choices=["upwind", "central"], default="upwind",
                     help="difference scheme of the anomaly (Sec. III.A upwind, Sec. III.D.2 central)")
     ap.add_argument("--diag-every", type=int, default=100)
@@ -615,7 +617,8 @@ def main():
     h = lbm.lbm_create(D, dims, w["gamma"], w["Pr"], w["mu"],
                        precision=lbm.LBM_FP32_DEV if word == 4 else lbm.LBM_FP64, bc=w["bc"],
                        visc_exponent=w["visc_exp"], T_ref=w["T_ref"], rho_ref=w["rho_ref"], u_ref=w["u_ref"],
-                       tile=tile, deriv_scheme=lbm.LBM_DERIV_CENTRAL if args.deriv == "central" else lbm.LBM_DERIV_UPWIND)
+                       tile=tile, deriv_scheme=lbm.LBM_DERIV_CENTRAL if args.deriv == "central" else lbm.LBM_DERIV_UPWIND,
+                       layout=lbm.LBM_LAYOUT_BLOCKS if args.layout == "blocks" else lbm.LBM_LAYOUT_SLOT_ROWS)
     lbm.lbm_set_stream(h, stream)
     lbm.lbm_init_fields(h, *(torch.from_numpy(a).to(dev) for a in w["fields"]))
     used_tile = lbm.lbm_get_tile(h)
@@ -679,7 +682,8 @@ def main():
 
     mlups = N * args.steps / wall / 1e6
     achieved = bytes_per_node * N / avg_kernel_s / 1e9
-    workload = w["label"].format(prec=args.precision) + (" central-anomaly" if args.deriv == "central" else "")
+    workload = (w["label"].format(prec=args.precision) + (" central-anomaly" if args.deriv == "central" else "")
+                + (" blocks-layout" if args.layout == "blocks" else ""))
     traffic = measured_traffic(workload, args.precision, used_tile)
     lattice = f"D{D}Q{Q}"
     out = {
@@ -697,7 +701,7 @@ def main():
         "data": "synthetic (seeded, no dataset)",
         "config": {"workload": workload, "lattice": lattice, "nodes": N, "dims": list(dims[:D]),
                    "bytes_per_node_update": bytes_per_node, "diag_every": args.diag_every,
-                   "tile": list(used_tile), "tile_source": "given" if tile else "default",
+                   "tile": list(used_tile), "tile_source": "given" if tile else "default", "layout": args.layout,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,

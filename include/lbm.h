@@ -60,6 +60,7 @@ enum { LBM_HOST = 0, LBM_DEVICE = 1 };
 /* Discrete derivative of the anomaly: first-order upwind (Sec. III.A) or
    second-order central (Sec. III.D.2). */
 enum { LBM_DERIV_UPWIND = 0, LBM_DERIV_CENTRAL = 1 };
+enum { LBM_LAYOUT_SLOT_ROWS = 0, LBM_LAYOUT_BLOCKS = 1 };
 enum {
   LBM_OK = 0,
   LBM_EINVAL = -1,    /* bad argument or field value */
@@ -84,6 +85,14 @@ typedef struct {
                            U(T) = its integral from 0, T recovered from U by Newton's method; needs
                            cv_poly[0] > 0 and cv_poly[1], cv_poly[2] >= 0.  All zero (default): the
                            constant C_v = 1/(gamma - 1), and gamma is used for nothing else */
+  int layout;           /* device layout of the populations of one march plane (x-y plane for D3Q27,
+                           x row for D2Q9), (f_i, g_i) pairs throughout:
+                           LBM_LAYOUT_SLOT_ROWS (default): slot i of the plane is one contiguous row of
+                           pairs (rows 64-pair aligned, staggered by 64 pairs);
+                           LBM_LAYOUT_BLOCKS: 64-node blocks, each holding its Q slots of 64 pairs one
+                           after the other.  Results are identical to the last bit; only the memory
+                           streams differ (a measurement choice).  The ABI state of lbm_get_state is
+                           the same for both. */
 } lbm_options;
 
 /* Fills *opt with the defaults above. */

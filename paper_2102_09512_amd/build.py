@@ -9,6 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
+# the same library with the step kernel's LDS filled with NaN before use (debug)
+POISON_LIB = os.path.join(HERE, "liblbm_poison.so")
 SOURCES = ["lbm_api.hip", "lbm_kernels.hip", "lbm_nn.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
@@ -20,23 +22,30 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = [hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        objs.append(obj)
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    for o in objs:
+
+
+def build(verbose: bool = False) -> str:
+    """Builds liblbm.so and its debug twin liblbm_poison.so (the step kernel
+    with LBM_POISON_LDS); returns the path of liblbm.so."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    objs = {}
+    for src in SOURCES:
+        obj = os.path.join(CSRC, src.replace(".hip", ".o"))
+        _run([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        objs[src] = obj
+    poison_obj = os.path.join(CSRC, "lbm_kernels_poison.o")
+    _run([hipcc, *HIPCC_FLAGS, "-DLBM_POISON_LDS=1", "-c", os.path.join(CSRC, "lbm_kernels.hip"), "-o", poison_obj],
+         verbose)
+    for lib, kernels in ((LIB, objs["lbm_kernels.hip"]), (POISON_LIB, poison_obj)):
+        tmp = lib + ".tmp"
+        _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, objs["lbm_api.hip"], kernels,
+              objs["lbm_nn.hip"]], verbose)
+        os.replace(tmp, lib)
+    for o in [*objs.values(), poison_obj]:
         os.remove(o)
     return LIB
 

@@ -275,15 +275,25 @@ int lbm_create(lbm_handle* out, int lattice, const int64_t dims[3], double gamma
       return fail(LBM_EINVAL, "lbm_create: cv_poly needs cv_poly[0] > 0 and cv_poly[1], cv_poly[2] >= 0 (finite)");
   const int64_t N = dims[0] * dims[1] * dims[2];
   if (N > ((int64_t)1 << 31) - 1024) return fail(LBM_EINVAL, "lbm_create: more than 2^31 nodes");
-  // plane-major layout (see StepParams): per march plane, Q slot arrays of
-  // (f, g) pairs, each 64-pair aligned and staggered by 64 pairs.  (Blocks of
-  // 64 nodes holding their Q slots one after the other, the same formula
-  // with sl = 128 and blk = 128 Q, measured within 1% of this layout for
-  // the step kernel and its access-pattern reference at 256^3.)
+  // plane-major layout (see StepParams).  Slot rows: per march plane, Q slot
+  // rows of (f, g) pairs, each 64-pair aligned and staggered by 64 pairs.
+  // Blocks: the same formula with 64-node blocks holding their Q slots of 64
+  // pairs one after the other (sl = 128, blk = 128 Q).
+  if (opt.layout != LBM_LAYOUT_SLOT_ROWS && opt.layout != LBM_LAYOUT_BLOCKS)
+    return fail(LBM_EINVAL, "lbm_create: unknown layout");
   const int64_t plane = lattice == 3 ? dims[0] * dims[1] : dims[0];
   const int64_t Qn = lattice == 2 ? 9 : 27;
-  const int64_t ps = ((plane + 63) / 64) * 64 + 64;
-  const int64_t sl = 2 * ps, blk = 128, ms = sl * Qn;
+  int64_t sl, blk, ms;
+  if (opt.layout == LBM_LAYOUT_SLOT_ROWS) {
+    const int64_t ps = ((plane + 63) / 64) * 64 + 64;
+    sl = 2 * ps;
+    blk = 128;
+    ms = sl * Qn;
+  } else {
+    sl = 128;
+    blk = 128 * Qn;
+    ms = ((plane + 63) / 64) * blk;
+  }
   // The step kernel addresses one march plane through a buffer resource with
   // 32-bit offsets.
   if (ms * (int64_t)word_of(opt.precision) >= ((int64_t)1 << 32))

@@ -40,6 +40,14 @@
 #include "lbm_internal.h"
 #include "lbm_node.h"
 
+// Debug build switch (liblbm_poison.so): fill the step kernel's LDS anomaly
+// ring with NaN at the start and before every plane refills its half, so
+// that a value read without having been written for the current plane shows
+// up as NaN in the results instead of a stale neighbour value.
+#ifndef LBM_POISON_LDS
+#define LBM_POISON_LDS 0
+#endif
+
 namespace lbm {
 
 __device__ inline int fix_coord(int k, int n, int bc) {
@@ -270,6 +278,19 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
   static_assert(D == 3 || BY == 1, "D2Q9 tiles are one row");
   __shared__ R lq0[2][BY][BX + 2];                    // anomaly along in-plane axis 0 (x)
   __shared__ R lq1[2][(D == 3) ? BY + 2 : 1][BX];     // anomaly along in-plane axis 1 (y, D3Q27 only)
+  // half b of the ring set to NaN by the whole work-group (debug build only;
+  // the caller separates it from the next reads or writes by a barrier)
+  auto poison = [&](int b) {
+    constexpr int N0 = BY * (BX + 2), N1 = ((D == 3) ? BY + 2 : 1) * BX;
+    const R nan = (R)__builtin_nan("");
+    for (int e = threadIdx.x; e < N0; e += BX * BY) (&lq0[b][0][0])[e] = nan;
+    for (int e = threadIdx.x; e < N1; e += BX * BY) (&lq1[b][0][0])[e] = nan;
+  };
+  if constexpr (LBM_POISON_LDS) {
+    poison(0);
+    poison(1);
+    __syncthreads();
+  }
 
   NodeConsts k = node_consts(p);
   k.caloric = CAL ? 1 : 0;
@@ -434,6 +455,11 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
   auto plane = [&](int m, R* fa, R* ga, NodeMoments<R>& ma, R* fb, R* gb, NodeMoments<R>& mb, R* fc, R* gc) {
     const int cb = (m - m0) & 1, nb = cb ^ 1;
     const bool more = m + 1 < m1;  // plane m + 1 collides in this chunk
+    if constexpr (LBM_POISON_LDS) {
+      // half nb was last read by plane m - 1, which ended with a barrier
+      poison(nb);
+      __syncthreads();
+    }
     if (PF2) {
       __amdgpu_buffer_rsrc_t rs[3];
       march_planes(more ? m + 2 : m + 1, rs);

@@ -22,12 +22,15 @@ except ImportError:  # host-only use (symbol checks) needs no torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
+# debug twin: the step kernel's LDS filled with NaN before use (tests only)
+POISON_LIB_PATH = os.path.join(_HERE, "liblbm_poison.so")
 
 LBM_D2Q9, LBM_D3Q27 = 2, 3
 LBM_FP64, LBM_FP32_DEV = 0, 1
 LBM_BC_PERIODIC, LBM_BC_ZERO_GRADIENT = 0, 1
 LBM_HOST, LBM_DEVICE = 0, 1
 LBM_DERIV_UPWIND, LBM_DERIV_CENTRAL = 0, 1
+LBM_LAYOUT_SLOT_ROWS, LBM_LAYOUT_BLOCKS = 0, 1
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 
 
@@ -41,7 +44,7 @@ class lbm_options(C.Structure):
     _fields_ = [
         ("precision", C.c_int), ("bc", C.c_int * 3), ("visc_exponent", C.c_double),
         ("T_ref", C.c_double), ("rho_ref", C.c_double), ("deriv_scheme", C.c_int),
-        ("tile", C.c_int * 3), ("u_ref", C.c_double * 3), ("cv_poly", C.c_double * 3),
+        ("tile", C.c_int * 3), ("u_ref", C.c_double * 3), ("cv_poly", C.c_double * 3), ("layout", C.c_int),
     ]
 
 
@@ -56,11 +59,11 @@ class lbm_diag(C.Structure):
     ]
 
 
-def _load():
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'` "
+def _load(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run `python -c 'import __graft_entry__ as g; g.build()'` "
                           "(hipcc for gfx950)")
-    L = C.CDLL(LIB_PATH)
+    L = C.CDLL(path)
     vp, i64, dp = C.c_void_p, C.c_int64, C.POINTER(C.c_double)
     L.lbm_default_options.argtypes = [C.POINTER(lbm_options)]
     L.lbm_default_options.restype = None
@@ -212,7 +215,7 @@ def lbm_default_options() -> lbm_options:
 
 def lbm_create(lattice, dims, gamma, Pr, mu, options: lbm_options | None = None, *, precision=None, bc=None,
                visc_exponent=None, T_ref=None, rho_ref=None, deriv_scheme=None, tile=None, u_ref=None,
-               cv_poly=None) -> int:
+               cv_poly=None, layout=None) -> int:
     o = options if options is not None else lbm_default_options()
     if precision is not None:
         o.precision = precision
@@ -236,6 +239,8 @@ def lbm_create(lattice, dims, gamma, Pr, mu, options: lbm_options | None = None,
     if cv_poly is not None:
         for k in range(3):
             o.cv_poly[k] = float(cv_poly[k])
+    if layout is not None:
+        o.layout = int(layout)
     d = (C.c_int64 * 3)(*[int(v) for v in (list(dims) + [1] * (3 - len(dims)))])
     h = C.c_void_p()
     _check(_L.lbm_create(C.byref(h), int(lattice), d, float(gamma), float(Pr), float(mu), C.byref(o)))
@@ -353,6 +358,12 @@ def lbm_device_copy(dst, src, nbytes: int, stream=None) -> int:
 def raw():
     """The ctypes library object (for the ABI tests)."""
     return _L
+
+
+def raw_poison():
+    """The debug twin liblbm_poison.so as a ctypes library with the same
+    argument types (its handles are used with its own functions only)."""
+    return _load(POISON_LIB_PATH)
 
 
 # ---- batches -----------------------------------------------------------------

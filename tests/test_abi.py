@@ -42,6 +42,7 @@ def test_default_options(lbm):
     assert o.visc_exponent == 0.0 and o.rho_ref == 1.0 and abs(o.T_ref - 1 / 3) < 1e-15
     assert o.deriv_scheme == lbm.LBM_DERIV_UPWIND and list(o.tile) == [0, 0, 0]
     assert list(o.u_ref) == [0.0, 0.0, 0.0]
+    assert o.layout == lbm.LBM_LAYOUT_SLOT_ROWS
 
 
 @pytest.mark.parametrize("args,needle", [
@@ -75,6 +76,7 @@ def test_create_rejects_bad_arguments(lbm, args, needle):
     (dict(tile=(64, 4, -2)), "tile"),
     (dict(u_ref=(1.5, 0.0, 0.0)), "u_ref"),
     (dict(u_ref=(0.0, float("nan"), 0.0)), "u_ref"),
+    (dict(layout=2), "layout"),
 ])
 def test_create_rejects_bad_options(lbm, kw, needle):
     with pytest.raises(lbm.LbmError) as e:
