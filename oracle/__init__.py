@@ -104,6 +104,8 @@ def lib():
         L.orc_collide_node.argtypes = [C.POINTER(_Params), _dp, _dp, _dp, _dp, _dp]
         L.orc_derivative.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
+        L.orc_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -122,6 +124,11 @@ def _vec(x, n=3):
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (results do not depend on it)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def Q(D: int) -> int:

@@ -86,6 +86,16 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads of the following parallel loops (n >= 1); the node arithmetic and
+   every summation order are the same for any count. */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Product form, Sec. II.B                                                  */
 /* ------------------------------------------------------------------------ */

@@ -110,6 +110,7 @@ int orc_diagnostics(const orc_sim* s, double* out /* ORC_NDIAG */);
 int orc_get_pops(const orc_sim* s, double* f, double* g);
 int orc_set_pops(orc_sim* s, const double* f, const double* g, long step);
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 
 /* ---- nodal building blocks (the functions the step itself uses) ---- */
 int orc_Q(int D);
