@@ -350,7 +350,8 @@ def test_shock_vortex_sound_field():
     what the set-up fixes on its own: the core of an isentropic vortex of Ma_v = 0.25 carries
     (1 - (gamma - 1) Ma_v^2 e / 2)^(gamma / (gamma - 1)) - 1 = -0.114 of the pressure around it; the sound it
     radiates on crossing the shock is quadrupolar (along theta = -45 deg and +45 deg from the vortex centre the
-    sound pressure has opposite signs lobe for lobe) and weak (the paper's "around 1 %"); and in the frame of the convected vortex its
+    sound pressure has opposite signs lobe for lobe) and weak (of the order of a percent of the pressure behind the
+    shock, as the paper reports); and in the frame of the convected vortex its
     fronts travel at the downstream sound speed sqrt(gamma T_2) of the Rankine-Hugoniot state."""
     lbm = _lbm()
     n, r_v, gamma, Ma_v = 1024, 32.0, 1.4, 0.25
