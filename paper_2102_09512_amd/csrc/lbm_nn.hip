@@ -241,8 +241,15 @@ __global__ void __launch_bounds__(64 * kW) conv_kernel(const __bf16* __restrict_
 // 14 products per output row instead of 27.  wq[p][o][k]: k < 8 channel k
 // of tap 2p, k >= 8 channel k - 8 of tap 2p + 1 (tap 27 does not exist: its
 // weights are zero and its B operand repeats tap 26).  Output as
-// conv_kernel (bf16 [v][32]).
+// conv_kernel (bf16 [v][32]).  PLANAR_IN: the input is read straight from
+// the FP32 planes x[c][v] (c < cin) and normalised as pack_input_kernel does
+// (the same expression, so the staged bf16 values are the same), for calls
+// that need no packed copy of it (inference).
+template <bool PLANAR_IN>
 __global__ void __launch_bounds__(64 * kW) conv_pair_kernel(const __bf16* __restrict__ in,
+                                                            const float* __restrict__ x, int cin,
+                                                            const float* __restrict__ mean,
+                                                            const float* __restrict__ inv_std,
                                                             const __bf16* __restrict__ wq,
                                                             const float* __restrict__ bias, int relu,
                                                             __bf16* __restrict__ out, int cout, const Grid g, int V) {
@@ -272,7 +279,13 @@ __global__ void __launch_bounds__(64 * kW) conv_pair_kernel(const __bf16* __rest
       if (node < NN) {
         const int hx = node % kHX, hy = (node / kHX) % kHY, hz = node / (kHX * kHY);
         const int gx = wrap(x0 + hx - 1, g.nx), gy = wrap(y0 + hy - 1, g.ny), gz = wrap(z0 + hz - 1, g.nz);
-        stage[k] = *(const bf8*)(in + (size_t)(gx + g.nx * (gy + g.ny * gz)) * 16);
+        const size_t v = (size_t)gx + (size_t)g.nx * (gy + (size_t)g.ny * gz);
+        if constexpr (PLANAR_IN) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c) stage[k][c] = (__bf16)(c < cin ? (x[(size_t)c * V + v] - mean[c]) * inv_std[c] : 0.f);
+        } else {
+          stage[k] = *(const bf8*)(in + v * 16);
+        }
       }
     }
 #pragma unroll
@@ -745,11 +758,18 @@ hipError_t conv(lbm_nn n, const __bf16* in, const __bf16* w, const float* bias, 
   return hipGetLastError();
 }
 
-// forward pass of normalised x into n->y; activations kept for the backward pass
-int nn_forward(lbm_nn n, const float* x) {
-  hipLaunchKernelGGL(lbmnn::pack_input_kernel, dim3((n->V + 255) / 256), dim3(256), 0, n->stream, x, n->ch[0],
-                     n->mean, n->inv_std, n->act[0], n->V);
-  NN_HIP(hipGetLastError(), "pack input");
+// forward pass of normalised x into yout (n->y if null); activations kept
+// for the backward pass.  keep_input: also keep the packed input (the weight
+// gradient of the first layer reads it); without it a first layer of at most
+// 8 channels reads x directly.
+int nn_forward(lbm_nn n, const float* x, float* yout = nullptr, bool keep_input = true) {
+  if (!yout) yout = n->y;
+  const bool direct = !keep_input && n->layers[0].wq && n->L > 1;
+  if (!direct) {
+    hipLaunchKernelGGL(lbmnn::pack_input_kernel, dim3((n->V + 255) / 256), dim3(256), 0, n->stream, x, n->ch[0],
+                       n->mean, n->inv_std, n->act[0], n->V);
+    NN_HIP(hipGetLastError(), "pack input");
+  }
   for (int l = 0; l < n->L; ++l) {
     const Layer& ly = n->layers[l];
     const bool last = l == n->L - 1;
@@ -758,18 +778,22 @@ int nn_forward(lbm_nn n, const float* x) {
     if (last && ly.wn) {
       const int blocks = (n->g.nx / lbmnn::kTX) * (n->g.ny / lbmnn::kTY) * (n->g.nz / lbmnn::kTZ);
       hipLaunchKernelGGL(lbmnn::conv_narrow_kernel, dim3(blocks), dim3(64 * lbmnn::kW), 0, n->stream, n->act[l], ly.wn,
-                         b, n->y, ly.cout, n->g, n->V);
+                         b, yout, ly.cout, n->g, n->V);
       e = hipGetLastError();
     } else if (ly.wq) {
       const int blocks = (n->g.nx / lbmnn::kTX) * (n->g.ny / lbmnn::kTY) * (n->g.nz / lbmnn::kTZ);
-      hipLaunchKernelGGL(lbmnn::conv_pair_kernel, dim3(blocks), dim3(64 * lbmnn::kW), 0, n->stream, n->act[l], ly.wq,
-                         b, 1, n->act[l + 1], ly.cout, n->g, n->V);
+      if (direct)
+        hipLaunchKernelGGL((lbmnn::conv_pair_kernel<true>), dim3(blocks), dim3(64 * lbmnn::kW), 0, n->stream, nullptr,
+                           x, n->ch[0], n->mean, n->inv_std, ly.wq, b, 1, n->act[l + 1], ly.cout, n->g, n->V);
+      else
+        hipLaunchKernelGGL((lbmnn::conv_pair_kernel<false>), dim3(blocks), dim3(64 * lbmnn::kW), 0, n->stream,
+                           n->act[l], nullptr, 0, nullptr, nullptr, ly.wq, b, 1, n->act[l + 1], ly.cout, n->g, n->V);
       e = hipGetLastError();
     } else if (ly.cinp == 16)
-      e = last ? conv<16, true>(n, n->act[l], ly.wp, b, 0, nullptr, n->y, ly.cout)
+      e = last ? conv<16, true>(n, n->act[l], ly.wp, b, 0, nullptr, yout, ly.cout)
                : conv<16, false>(n, n->act[l], ly.wp, b, 1, nullptr, n->act[l + 1], ly.cout);
     else
-      e = last ? conv<32, true>(n, n->act[l], ly.wp, b, 0, nullptr, n->y, ly.cout)
+      e = last ? conv<32, true>(n, n->act[l], ly.wp, b, 0, nullptr, yout, ly.cout)
                : conv<32, false>(n, n->act[l], ly.wp, b, 1, nullptr, n->act[l + 1], ly.cout);
     NN_HIP(e, "conv forward");
   }
@@ -985,10 +1009,8 @@ int lbm_nn_forward(lbm_nn n, const float* x, float* y) {
   if (!n || !x || !y) return nn_fail(LBM_EINVAL, "lbm_nn_forward: NULL argument");
   int rc = nn_select(n);
   if (rc) return rc;
-  if ((rc = nn_forward(n, x))) return rc;
-  NN_HIP(hipMemcpyAsync(y, n->y, sizeof(float) * (size_t)n->V * n->ch[n->L], hipMemcpyDeviceToDevice, n->stream),
-         "copy output");
-  return LBM_OK;
+  // inference: the first layer reads x directly and the last writes y
+  return nn_forward(n, x, y, false);
 }
 
 int lbm_nn_loss_backward(lbm_nn n, const float* x, const float* target, double* loss) {
@@ -1112,7 +1134,7 @@ int lbm_nn_correct(lbm_nn n, lbm_handle h) {
                        F + 4 * (size_t)V, D, V, n->fld);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) rc = nn_hip(e, "fields kernel");
-    if (rc == LBM_OK) rc = nn_forward(n, n->fld);
+    if (rc == LBM_OK) rc = nn_forward(n, n->fld, nullptr, false);
     if (rc == LBM_OK) {
       hipLaunchKernelGGL(lbmnn::output_to_increments_kernel, dim3((V + 255) / 256), dim3(256), 0, n->stream, n->y,
                          n->out_std, n->ch[n->L], n->out_off, D, (float)n->limit, V, drho, du, dT);
