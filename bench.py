@@ -99,16 +99,22 @@ def measured_traffic(workload: str, precision: str, tile):
     return None
 
 
-def make_workload(name: str, n: int):
+def make_workload(name: str, n: int, re_lambda: float = 72.0, ma_t: float = 0.5):
     """Inputs and physical parameters of a workload (seeded, synthetic)."""
     from paper_2102_09512_amd import inputs
 
     if name == "turbulence3d":
-        fields = inputs.turbulence(3, n, seed=0, k0_index=4, Ma_t=0.5, T0=0.15)
-        mu = inputs.turbulence_viscosity(n, k0_index=4, Ma_t=0.5, T0=0.15, Re_lambda=72.0)
+        if n <= 256:
+            fields = inputs.turbulence(3, n, seed=0, k0_index=4, Ma_t=ma_t, T0=0.15)
+            draw = ""
+        else:  # the same spectrum from a 64^3 draw sampled on the grid (a full draw at n^3 takes minutes)
+            fields = inputs.turbulence_fine(n, seed=0, n_gen=64, k0_index=4, Ma_t=ma_t, T0=0.15)
+            draw = " (64^3 draw sampled on the grid)"
+        mu = inputs.turbulence_viscosity(n, k0_index=4, Ma_t=ma_t, T0=0.15, Re_lambda=re_lambda)
         return dict(D=3, dims=(n, n, n), fields=fields, gamma=1.4, Pr=0.7, mu=mu, visc_exp=0.76, T_ref=0.15,
                     rho_ref=1.0, u_ref=None, bc=(0, 0, 0),
-                    label=f"decaying-turbulence D3Q27 {n}^3 periodic {{prec}}-storage Ma_t=0.5 Re_lambda=72")
+                    label=f"decaying-turbulence D3Q27 {n}^3 periodic {{prec}}-storage Ma_t={ma_t:g} "
+                          f"Re_lambda={re_lambda:g}{draw}")
     rho, u, T, _ = inputs.shock_vortex(n, n, r_v=32.0 * n / 1024, x_s=n // 2)
     return dict(D=2, dims=(n, n, 1), fields=(rho, u, T), gamma=1.4, Pr=0.75, mu=0.0198, visc_exp=0.0, T_ref=0.05,
                 rho_ref=1.0, u_ref=(float(u[0, 0, 0, 0]), 0.0), bc=(1, 0, 0),
@@ -592,6 +598,11 @@ def main():
                     help="ensemble2d: also time every tile width, march chunk and launch form (tile_sweep)")
     ap.add_argument("--n", type=int, default=0, help="box edge (default 256 for turbulence3d, 1024 for shockvortex2d)")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--re-lambda", type=float, default=72.0,
+                    help="turbulence3d: Taylor Reynolds number that sets the viscosity (mu grows with n)")
+    ap.add_argument("--ma-t", type=float, default=0.5,
+                    help="turbulence3d: turbulent Mach number (at 640^3 and above, 0.5 leaves the method's stable "
+                         "range within 30-110 steps: its supersonic patches no longer decay)")
     ap.add_argument("--tile", type=str, default="", help="bx,by,chunk of the step kernel")
     ap.add_argument("--layout", choices=["rows", "blocks"], default="rows",
                     help="device layout of the populations (lbm_options.layout): slot rows or 64-node blocks")
@@ -634,7 +645,7 @@ def main():
         return
     n = args.n or (256 if args.workload == "turbulence3d" else 1024)
     _log(f"[bench] generating the {args.workload} input, n = {n}")
-    w = make_workload(args.workload, n)
+    w = make_workload(args.workload, n, args.re_lambda, args.ma_t)
     D, dims = w["D"], w["dims"]
     N = dims[0] * dims[1] * dims[2]
     Q = 3 ** D
@@ -748,9 +759,13 @@ def main():
         "kernel_source": kernel_source_hash(),
         "final_step_nonfinite": d["nonfinite"],
     }
-    if D == 2:
+    if bytes_per_node * N <= 256 * 2 ** 20:  # both population buffers
         out["roofline"]["note"] = "working set fits in the last-level cache; not an HBM roofline figure"
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and N > 256 ** 3:
+        _log("[bench] no CPU baseline above 256^3 nodes (the whole-field oracle would need "
+             f"{N * 2 * 2 * Q * 8 / 1e9:.0f} GB of host memory)")
+        out["cpu_baseline"] = None
+    elif not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
         out["cpu_baseline"]["gpu_speedup"] = round(mlups / out["cpu_baseline"]["value"], 1)
     if args.workload == "turbulence3d" and n == 256 and not args.no_learned:

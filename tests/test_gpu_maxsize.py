@@ -1,0 +1,157 @@
+"""The largest grids of the benchmark's family that one device holds, in the
+launch shape the library picks for them:
+
+* D3Q27 768^3 with FP32 deviation storage: 453 M nodes, 196 GB of
+  populations;
+* D3Q27 640^3 with FP64 storage: 262 M nodes, 226 GB of populations.
+
+At these sizes the element offsets into the population buffers pass 2^31,
+and one buffer holds many times 4 GiB.  The input is the benchmark's initial
+spectrum (E ~ k^4 exp(-2 (k/k0)^2), k0 = 4, Ma_t 0.5, Re_lambda 72): the
+turbulence draw of a 64^3 grid, sampled on the fine grid.
+
+After two steps from the equilibria of those fields, the moments rho, u, T
+at about 1,000 sampled nodes are checked against the oracle. The samples are
+tile and chunk edges, the planes where offsets into a buffer pass 2^31
+elements and 2^32 to 2^35 bytes, and random nodes.  The oracle steps a 9^3 periodic patch cut
+out of the same fields around each sampled node.  After two steps the
+moments of a node depend only on the initial state within three nodes of it,
+so the patch's own periodic wrap never reaches its centre
+(tests/oracle_patch.py; tests/test_oracle_patch.py checks the reduction
+against the whole-field oracle).
+
+For FP32 storage the oracle applies its FP32 storage model (each stored value
+is the reference state plus its deviation rounded to single precision).
+Where a velocity component that sets one of the step-1 upwind sides is within
+FP32 resolution of zero, both sides are valid, and the node must match the
+oracle's plain run or its run with those sides reversed.
+
+The totals of mass, momentum and energy at initialisation are checked against sums
+of the input fields (FP64 on the host).  Mass, momentum and energy after two
+steps must equal the initial totals (periodic box)."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle_floor
+import oracle_patch
+from paper_2102_09512_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GB = 1e9
+
+
+def _lbm():
+    from paper_2102_09512_amd import lbm
+
+    return lbm
+
+
+def _samples(n, chunk, word, seed):
+    """Node indices: in-plane tile edges (64-wide, 4- and 8-row tiles), the
+    first and last planes and both sides of every march-chunk edge, the
+    planes where the offset into a buffer first passes 2^31 elements and
+    2^32 ... 2^35 bytes (plane stride of the slot-row layout: 2 Q words per
+    node of a plane padded to 64 nodes, plus 64), and random nodes."""
+    xs = [0, 63, 64, n // 2, n - 64, n - 1]
+    ys = [0, 3, 4, 8, n // 2, n - 1]
+    zs = {0, 1, n - 2, n - 1}
+    for c in range(chunk, n, chunk):
+        zs |= {c - 1, c}
+    plane_words = 2 * 27 * ((n * n + 63) // 64 * 64 + 64)
+    for lim in [2 ** 31 * word] + [2 ** b for b in range(32, 36)]:
+        m = lim // (plane_words * word)
+        if m < n:
+            zs |= {m, min(m + 1, n - 1)}
+    zz, yy, xx = np.meshgrid(sorted(zs), ys, xs, indexing="ij")
+    structured = (xx + n * (yy + n * zz)).ravel()
+    rand = np.random.default_rng(seed).integers(0, n ** 3, size=400)
+    return np.unique(np.concatenate([structured, rand])).astype(np.int64)
+
+
+@pytest.mark.parametrize("n,fp32", [(768, True), (640, False)])
+def test_largest_grid_sampled_moments(n, fp32):
+    lbm = _lbm()
+    word = 4 if fp32 else 8
+    N = n ** 3
+    need = N * (2 * 54 * word + 6 * 8 + 5 * 8) + 4 * GB  # populations, moment scratch, fields, slack
+    free, total = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip(f"needs {need / GB:.0f} GB of device memory, {free / GB:.0f} GB free")
+    print(f"[gpu case] largest grid D3Q27 {n}^3 fp32={fp32}: {N * 2 * 54 * word / GB:.0f} GB of populations, "
+          f"{free / GB:.0f} GB free", flush=True)
+    fields = I.turbulence_fine(n, seed=0, n_gen=64, k0_index=4, Ma_t=0.5, T0=0.15)
+    mu = I.turbulence_viscosity(n, k0_index=4, Ma_t=0.5, T0=0.15, Re_lambda=72.0)
+    rho, u, T = fields
+    ke = 0.5 * rho * (u ** 2).sum(0)
+    host_mass = float(rho.sum())
+    host_mom = [float((rho * u[a]).sum()) for a in range(3)]
+    host_energy = float((rho * 2.5 * T + ke).sum())
+    del ke
+    umax = float(np.abs(u).max())
+    print(f"  fields generated; max |u| {umax:.3f}", flush=True)
+
+    h = lbm.lbm_create(3, (n, n, n), 1.4, 0.7, mu, precision=lbm.LBM_FP32_DEV if fp32 else lbm.LBM_FP64,
+                       visc_exponent=0.76, T_ref=0.15, rho_ref=1.0)
+    try:
+        tile = lbm.lbm_get_tile(h)
+        lbm.lbm_set_stream(h, torch.cuda.current_stream())
+        dev = [torch.from_numpy(a).cuda() for a in fields]
+        lbm.lbm_init_fields(h, *dev)
+        d0 = lbm.lbm_diagnostics(h)
+        lbm.lbm_step(h, 2)
+        lbm.lbm_moments(h, *dev)  # the input tensors take the moments
+        d2 = lbm.lbm_diagnostics(h)
+        torch.cuda.synchronize()
+        print(f"  launch tile {tile}; two steps done", flush=True)
+        nodes = _samples(n, tile[2], word, seed=5)
+        idx = torch.from_numpy(nodes).cuda()
+        got = (dev[0].reshape(-1)[idx].cpu().numpy(), dev[1].reshape(3, -1)[:, idx].cpu().numpy(),
+               dev[2].reshape(-1)[idx].cpu().numpy())
+        del dev, idx
+    finally:
+        lbm.lbm_destroy(h)
+    torch.cuda.empty_cache()
+
+    # totals: initial against the input fields, and conservation over the two steps
+    tol0 = 1e-7 if fp32 else 1e-12
+    assert d0["nonfinite"] == 0 and d2["nonfinite"] == 0
+    assert abs(d0["mass"] - host_mass) <= tol0 * host_mass, (d0["mass"], host_mass)
+    for a in range(3):
+        assert abs(d0["momentum"][a] - host_mom[a]) <= tol0 * host_mass * umax, (a, d0["momentum"][a], host_mom[a])
+    assert abs(d0["energy"] - host_energy) <= tol0 * host_energy, (d0["energy"], host_energy)
+    assert abs(d2["mass"] - d0["mass"]) <= 1e-9 * d0["mass"]
+    assert abs(d2["energy"] - d0["energy"]) <= 1e-9 * d0["energy"]
+    for a in range(3):
+        assert abs(d2["momentum"][a] - d0["momentum"][a]) <= 1e-9 * d0["mass"] * umax
+
+    # sampled moments against the oracle's patches
+    if fp32:
+        rest = oracle_floor.fp32_reference(3, rho_ref=1.0, T_ref=0.15)
+        band = 2.0 ** -20 * umax
+    else:
+        rest, band = None, 1e-13 * umax
+    print(f"  oracle on {nodes.size} patches of 9^3 ...", flush=True)
+    sim_kw = dict(gamma=1.4, Pr=0.7, mu=mu, visc_exp=0.76, T_ref=0.15)
+    scale = (1.0, umax, 0.15)
+    worst = [0.0, 0.0, 0.0]
+    ambiguous = 0
+    for k, node in enumerate(nodes):
+        plain, _, alt = oracle_patch.two_step_moments(fields, node, n, sim_kw, rest, band)
+        g = (got[0][k], got[1][:, k], got[2][k])
+        errs = [float(np.max(np.abs(np.asarray(g[j]) - np.asarray(plain[j])))) / scale[j] for j in range(3)]
+        if alt is not None:
+            ambiguous += 1
+            e_alt = [float(np.max(np.abs(np.asarray(g[j]) - np.asarray(alt[j])))) / scale[j] for j in range(3)]
+            if max(e_alt) < max(errs):
+                errs = e_alt
+        worst = [max(w, e) for w, e in zip(worst, errs)]
+        if (k + 1) % 400 == 0:
+            print(f"  {k + 1} patches, worst so far rho {worst[0]:.2e} u {worst[1]:.2e} T {worst[2]:.2e}", flush=True)
+    print(f"  sampled moments after 2 steps: rho {worst[0]:.2e}, u {worst[1]:.2e}, T {worst[2]:.2e} "
+          f"(relative to 1, max |u| and T0); {ambiguous} nodes with an ambiguous upwind side", flush=True)
+    bar = 1e-5 if fp32 else 1e-12
+    assert max(worst) <= bar, worst
