@@ -361,6 +361,12 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
   // in flight for every shape: the best latency hiding the access pattern
   // allows.
   constexpr bool PF2 = PAT || (DEV && BX * BY <= 256);
+  // One plane in flight in a 512-thread group (two wavefronts per SIMD, both
+  // of this group): the next core loads are issued before the barrier that
+  // ends a plane, so their latency overlaps the wait for the wavefronts that
+  // pull halo nodes.  At one wavefront per SIMD (256 threads) issuing them at
+  // the top of the plane measured faster.
+  constexpr bool EARLY = !PF2 && BX * BY > 256;
   const unsigned slot_bytes = (unsigned)(p.sl * (long long)sizeof(S));
   const long long plane_bytes = sm * (long long)sizeof(S);
   // byte offsets of the 9 in-plane sources of the core and of the halo node
@@ -441,17 +447,21 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     core_publish(mo0, 0);
     halo_direct(rs, 0);
   }
-  if (PF2) {
+  {
     __amdgpu_buffer_rsrc_t rs[3];
     march_planes(m0 + 1, rs);
-    pull<D, S, R>(rs, slot_bytes, clo, f1, g1);
-    if (has_halo) pull<D, S, R>(rs, slot_bytes, hlo, hf, hg);
+    if (PF2 || EARLY) pull<D, S, R>(rs, slot_bytes, clo, f1, g1);
+    if (PF2 && has_halo) pull<D, S, R>(rs, slot_bytes, hlo, hf, hg);
   }
   __syncthreads();
 
-  // One plane: collide plane m (fa, ga, ma), finish plane m + 1 (fb, gb, mb),
-  // issue the loads of plane m + 2 into (fc, gc) (PF2) or of plane m + 1
-  // (otherwise).  The three register sets rotate through the unrolled loop.
+  // One plane: collide plane m (fa, ga, ma) and finish plane m + 1 (fb, gb,
+  // mb).  PF2: plane m + 1's loads were issued one plane earlier, and the
+  // loads of plane m + 2 (core and halo) go into (fc, gc) before the
+  // collision; the three register sets rotate through a 3-way unrolled loop.
+  // One plane in flight: plane m + 1 moves into (fa, ga) once plane m is
+  // stored; its core loads were issued at the end of the previous plane
+  // (EARLY) or at the top of this one.
   auto plane = [&](int m, R* fa, R* ga, NodeMoments<R>& ma, R* fb, R* gb, NodeMoments<R>& mb, R* fc, R* gc) {
     const int cb = (m - m0) & 1, nb = cb ^ 1;
     const bool more = m + 1 < m1;  // plane m + 1 collides in this chunk
@@ -471,14 +481,23 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
       if (more && has_halo) pull<D, S, R>(rs, slot_bytes, hlo, hf, hg);
     } else {
       // one plane in flight: the halo loads follow the core moments, so the
-      // two sets of populations are not live together
+      // halo node's populations and plane m + 2's are not live together
       __amdgpu_buffer_rsrc_t rs[3];
       march_planes(m + 1, rs);
-      pull<D, S, R>(rs, slot_bytes, clo, fb, gb);
-      mb = moments(fb, gb);
-      qm_next = anom(mb, D - 1);
-      core_publish(mb, nb);
-      halo_direct(rs, nb);
+      if constexpr (EARLY) {
+        // the halo first: its nodes are the neighbouring tiles' core, whose
+        // loads were issued just before the barrier, so they still hit L2
+        halo_direct(rs, nb);
+        mb = moments(fb, gb);
+        qm_next = anom(mb, D - 1);
+        core_publish(mb, nb);
+      } else {
+        pull<D, S, R>(rs, slot_bytes, clo, fb, gb);
+        mb = moments(fb, gb);
+        qm_next = anom(mb, D - 1);
+        core_publish(mb, nb);
+        halo_direct(rs, nb);
+      }
     }
     // collide plane m
     R dd[3];
@@ -503,6 +522,21 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         Buf<S>::store(v, rd, o, (unsigned)i * slot_bytes);
       }
     }
+    if (!PF2) {
+      // plane m + 1 becomes the next collision set (EARLY: plane m + 2's
+      // loads go into the freed set now)
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        fa[i] = fb[i];
+        ga[i] = gb[i];
+      }
+      ma = mb;
+      if (EARLY && more) {
+        __amdgpu_buffer_rsrc_t rs[3];
+        march_planes(m + 2, rs);
+        pull<D, S, R>(rs, slot_bytes, clo, fb, gb);
+      }
+    }
     __syncthreads();
     qm_prev = qm_cur;
     qm_cur = qm_next;
@@ -518,15 +552,8 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
       plane(m + 2, f2, g2, mo2, f0, g0, mo0, f1, g1);
     }
   } else {
-    for (int m = m0; m < m1; ++m) {
-      plane(m, f0, g0, mo0, f1, g1, mo1, f2, g2);
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        f0[i] = f1[i];
-        g0[i] = g1[i];
-      }
-      mo0 = mo1;
-    }
+    // plane m in set 0, plane m + 1 in flight in set 1
+    for (int m = m0; m < m1; ++m) plane(m, f0, g0, mo0, f1, g1, mo1, f2, g2);
   }
 }
 
