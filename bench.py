@@ -7,6 +7,13 @@ solenoidal velocity with E(k) ~ k^4 exp(-2 (k/k0)^2), k0 = 4 (2 pi/256),
 Ma_t = 0.5, Re_lambda = 72, rho = 1, T0 = 0.15, mu = mu0 (T/T0)^0.76,
 Pr = 0.7, gamma = 1.4.
 
+--n (turbulence3d): another box edge.  Above 256 the field is the same
+spectrum from a 64^3 draw sampled on the grid (a full draw at that size takes
+minutes), and no CPU baseline is taken (the whole-field oracle would not fit
+in host memory).  768^3 FP32 and 640^3 FP64 are the largest grids one device
+holds.  --ma-t and --re-lambda change the flow: at 640^3 and above, Ma_t 0.5
+leaves the method's stable range within 30-110 steps.
+
 --workload shockvortex2d: the 2-D shock-vortex interaction, D2Q9 1024^2 (a
 standing Ma 1.2 shock at x = 512 with an isentropic vortex upstream); its
 FP32 working set (151 MB) fits in the 256 MB last-level cache, so its HBM
