@@ -956,11 +956,18 @@ static hipError_t launch_step_t(const Ctx& c, const void* src, void* dst) {
 // the time of one tile plane of the shape relative to 64 x 4: 32 x 8 moves
 // the same nodes a little slower (1.02), 64 x 8 moves twice the nodes with
 // two wavefronts per SIMD hiding more latency (1.8).
-static double march_cost(const int64_t n[3], int bx, int by, int64_t chunk, double w) {
+static double march_cost(const int64_t n[3], int bx, int by, int64_t chunk, double w, double pro) {
   const int64_t tiles = ((n[0] + bx - 1) / bx) * ((n[1] + by - 1) / by);
   const int64_t blocks = tiles * ((n[2] + chunk - 1) / chunk);
-  return (double)((blocks + 255) / 256) * (double)(chunk + 8) * w;
+  return (double)((blocks + 255) / 256) * ((double)chunk + pro) * w;
 }
+
+// Per-plane cost w and chunk prologue pro (in planes) of a 3-D launch shape,
+// fitted to tile and chunk sweeps: 64 x 4 (1, 8 planes), 32 x 8 (1.02, 8)
+// and the 512-thread 64 x 8 (1.82, 4.45; its next plane's loads are issued
+// before the per-plane barrier, which shortens its prologue: fitted to
+// 256^3 in 128-plane chunks and a 256 x 256 x 32 slab in 16-plane chunks).
+static double shape_prologue(int bx, int by) { return (bx == 64 && by == 8) ? 4.45 : 8.0; }
 
 // The power-of-two chunk of 4 to 256 planes, or the whole march axis, with
 // the lowest march_cost for one 3-D launch shape.  Chunks stay powers of
@@ -969,9 +976,10 @@ static double march_cost(const int64_t n[3], int bx, int by, int64_t chunk, doub
 static int64_t best_chunk3(const int64_t n[3], int bx, int by, double w, double* cost) {
   int64_t best = 1;
   double best_cost = -1.0;
+  const double pro = shape_prologue(bx, by);
   for (int64_t chunk = 4;; chunk *= 2) {
     const int64_t c = chunk < n[2] ? chunk : n[2];
-    const double k = march_cost(n, bx, by, c, w);
+    const double k = march_cost(n, bx, by, c, w, pro);
     if (best_cost < 0.0 || k < best_cost) {
       best_cost = k;
       best = c;
@@ -999,15 +1007,16 @@ int default_chunk(int D, const int64_t n[3], int bx, int by) {
 // storage, 64 x 8 (the only 512-thread shape that fits 256 registers
 // without spilling); the caloric variant is compiled for 64 x 4 only.  On
 // one MI355X this picks 64 x 4 with 4-plane chunks at 64^3 (2.1x the
-// throughput of 16-plane chunks), 32 x 8 / 16 at 96^3, 64 x 4 / 32 at
-// 128^3, 64 x 8 / 64 at 192^3 and 64 x 8 / 128 at 256^3 (5% faster than
-// 64 x 4 / 256 there).  D2Q9: rows of 128, or of 256 from 1024 nodes per row
+// throughput of 16-plane chunks), 32 x 8 / 16 at 96^3, 64 x 8 / 16 at 128^3
+// (3.6% faster than 64 x 4 / 32), 64 x 8 / 64 at 192^3, 64 x 8 / 128 at
+// 256^3 (9% faster than 64 x 4 / 256 there) and 64 x 8 / 16 for a
+// 256 x 256 x 32 slab (8% faster than 64 x 4 / 32).  D2Q9: rows of 128, or of 256 from 1024 nodes per row
 // (FP32: 9% faster at 4096^2, even at 1024^2 and 2048^2; FP64 at 1024^2: 4%
 // faster).
 Tile default_tile(int D, int precision, const int64_t n[3], bool caloric) {
   if (D == 3) {
     struct Shape { int bx, by; double w; };
-    const Shape shapes[3] = {{64, 4, 1.0}, {32, 8, 1.02}, {64, 8, 1.8}};
+    const Shape shapes[3] = {{64, 4, 1.0}, {32, 8, 1.02}, {64, 8, 1.82}};
     const int nshapes = caloric ? 1 : (precision == LBM_FP32_DEV ? 3 : 2);
     Tile best{64, 4, 1};
     double best_cost = -1.0;
