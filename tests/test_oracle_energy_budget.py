@@ -21,6 +21,7 @@ lattice's own dissipation at this resolution.  The bar is 5 %.  Planted in a
 copy of the oracle, the g rate in place of the f rate gives 1.72, and a
 relaxation rate built from mu / rho instead of mu / p gives 0.16."""
 import numpy as np
+import pytest
 
 import oracle
 from paper_2102_09512_amd import inputs as I
@@ -38,10 +39,11 @@ def _enstrophy_sum(u, n):
     return float((np.abs(wx) ** 2 + np.abs(wy) ** 2 + np.abs(wz) ** 2).sum() / n ** 3)
 
 
-def test_kinetic_energy_budget_of_decaying_turbulence():
+@pytest.mark.parametrize("deriv", [oracle.UPWIND, oracle.CENTRAL])
+def test_kinetic_energy_budget_of_decaying_turbulence(deriv):
     n, mu, every, t0, t1 = 48, 0.02, 5, 50, 300
     fields = I.turbulence(3, n, seed=2, k0_index=2, Ma_t=0.1, T0=0.15)
-    s = oracle.Sim(3, (n, n, n), gamma=1.4, Pr=0.7, mu=mu, visc_exp=0.0, T_ref=0.15)
+    s = oracle.Sim(3, (n, n, n), gamma=1.4, Pr=0.7, mu=mu, visc_exp=0.0, T_ref=0.15, deriv=deriv)
     s.init(*fields)
     times, kin, diss = [], [], []
     for step in range(t1 + 1):
