@@ -270,7 +270,55 @@ __global__ void __launch_bounds__(64 * kW) conv_pair_kernel(const __bf16* __rest
     const int c = 8 * (i >> 2) + 4 * half + (i & 3);
     bo[i] = bias && c < cout ? bias[c] : 0.f;
   }
-  {
+  if constexpr (PLANAR_IN) {
+    // Rows (hy, hz) of the halo block: the 32 interior nodes of a row are 8
+    // aligned groups of 4 consecutive x (one 16-byte load per channel; x0
+    // and nx are multiples of 32), its two end nodes (x0 - 1 and x0 + 32,
+    // wrapped) are loaded one by one.
+    constexpr int PER_ROW = kTX / 4 + 2, ITEMS = kHZ * kHY * PER_ROW;
+    constexpr int NIT = (ITEMS + 64 * kW - 1) / (64 * kW);
+    float4 xs[NIT][8];
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int item = threadIdx.x + k * 64 * kW;
+      if (item < ITEMS) {
+        const int row = item / PER_ROW, e = item % PER_ROW, hy = row % kHY, hz = row / kHY;
+        const int gy = wrap(y0 + hy - 1, g.ny), gz = wrap(z0 + hz - 1, g.nz);
+        const int gx = e < kTX / 4 ? x0 + 4 * e : wrap(e == kTX / 4 ? x0 - 1 : x0 + kTX, g.nx);
+        const size_t v = (size_t)gx + (size_t)g.nx * (gy + (size_t)g.ny * gz);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          xs[k][c] = float4{0.f, 0.f, 0.f, 0.f};
+          if (c < cin) {
+            if (e < kTX / 4) xs[k][c] = *(const float4*)(x + (size_t)c * V + v);
+            else xs[k][c].x = x[(size_t)c * V + v];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int item = threadIdx.x + k * 64 * kW;
+      if (item < ITEMS) {
+        const int row = item / PER_ROW, e = item % PER_ROW;
+        const int base = row * kHX;  // node index of hx = 0 in this row
+        // normalised as pack_input_kernel does (the same expression, so the staged bf16 values are the same)
+        auto node_chunk = [&](int n) {
+          bf8 val;
+#pragma unroll
+          for (int c = 0; c < 8; ++c) val[c] = (__bf16)(c < cin ? (xs[k][c][n] - mean[c]) * inv_std[c] : 0.f);
+          return val;
+        };
+        if (e < kTX / 4) {
+#pragma unroll
+          for (int n = 0; n < 4; ++n) *(bf8*)(tile + (base + 4 * e + n + 1) * 8) = node_chunk(n);
+        } else {
+          *(bf8*)(tile + (base + (e == kTX / 4 ? 0 : kHX - 1)) * 8) = node_chunk(0);
+        }
+      }
+    }
+    __syncthreads();
+  } else {
     constexpr int NIT = (NN + 64 * kW - 1) / (64 * kW);
     bf8 stage[NIT];
 #pragma unroll
@@ -279,13 +327,7 @@ __global__ void __launch_bounds__(64 * kW) conv_pair_kernel(const __bf16* __rest
       if (node < NN) {
         const int hx = node % kHX, hy = (node / kHX) % kHY, hz = node / (kHX * kHY);
         const int gx = wrap(x0 + hx - 1, g.nx), gy = wrap(y0 + hy - 1, g.ny), gz = wrap(z0 + hz - 1, g.nz);
-        const size_t v = (size_t)gx + (size_t)g.nx * (gy + (size_t)g.ny * gz);
-        if constexpr (PLANAR_IN) {
-#pragma unroll
-          for (int c = 0; c < 8; ++c) stage[k][c] = (__bf16)(c < cin ? (x[(size_t)c * V + v] - mean[c]) * inv_std[c] : 0.f);
-        } else {
-          stage[k] = *(const bf8*)(in + v * 16);
-        }
+        stage[k] = *(const bf8*)(in + ((size_t)gx + (size_t)g.nx * (gy + (size_t)g.ny * gz)) * 16);
       }
     }
 #pragma unroll
